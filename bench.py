@@ -1,0 +1,210 @@
+"""Benchmark: batched ln L + gradient of the dark-siren likelihood on one MI355X.
+
+Workload (one step): the O5-like catalogue -- 5000 events with U[1000, 8192]
+posterior samples each, 32-2048 sky pixels per event with 1024-node LOS
+tables (about 10 GB in HBM), 1e7 detected injections -- evaluated for a
+batch of 64 hyperparameter points drawn from the prior box, returning ln L
+and d ln L / d Lambda (all 16 entries) in one call of dsl_loglike_grad.
+
+Prints one JSON line.  `value` = Lambda-evaluations (ln L + gradient) per
+second; the roofline object reports the dominant kernel (the fused weight +
+adjoint sweep) against the FP32 vector peak; cpu_baseline is the FP64 oracle
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per sample-weight (one sample or injection, one Lambda):
+# floating-point operations of the weight formula as the sweep evaluates it
+# (add/mul = 1, fused multiply-add = 2, each exp2/log2/rcp/rsqrt/sqrt = 1),
+# counted from the source; see the design doc for the breakdown.
+FLOP_PER_WEIGHT_FWD = 175
+FLOP_PER_WEIGHT_GRAD = 360
+PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
+PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--config", default="c4")
+    p.add_argument("--B", type=int, default=64)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-single", action="store_true", help="skip the one-Lambda-per-launch comparison")
+    p.add_argument("--autotune", action="store_true")
+    p.add_argument("--forward-only", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(cat, lam_row, grad):
+    """The oracle on a bounded sample of the workload, scaled to one full Lambda."""
+    import numpy as np
+    import torch
+    from oracle import dsl_oracle as O
+    n_ev = 40
+    n_inj = 2_000_000
+    sub = cat.subset(np.arange(n_ev), inj=slice(0, n_inj))
+    t0 = time.perf_counter()
+    O.loglike(sub, lam_row, grad=grad)
+    dt = time.perf_counter() - t0
+    w_sub = sub.n_samp + sub.n_inj
+    w_full = cat.n_samp + cat.n_inj
+    per_lambda_s = dt * w_full / w_sub
+    return {"value": 1.0 / per_lambda_s, "unit": "Lambda-evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle ({'ln L + autograd gradient' if grad else 'ln L'}) on the first {n_ev} events "
+                      f"({sub.n_samp} samples) and first {n_inj} injections for 1 Lambda: {dt:.2f} s, "
+                      f"scaled by {w_full}/{w_sub} sample-weights to one full-catalogue Lambda"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2605_23538_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    grad = not args.forward_only
+    t0 = time.time()
+    cat = synth.make_catalog(args.config)
+    print(f"# generated {args.config}: {cat.n_events} events, {cat.n_pix} pixels, {cat.n_samp} samples, "
+          f"{cat.n_inj} injections, LOS {cat.los.nbytes / 1e9:.2f} GB in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    t0 = time.time()
+    lik = binding.DarkSirenLikelihood(cat, precision="fp32")
+    print(f"# uploaded in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    B = args.B
+    lam_np = synth.lambdas_for(args.config, B)
+    lam = torch.tensor(lam_np, device="cuda:0")
+    if args.autotune:
+        lik.autotune(B, grad)
+    dev = lam.device
+    logL = torch.empty(B, dtype=torch.float64, device=dev)
+    g = torch.empty(B, 16, dtype=torch.float64, device=dev)
+    flags = torch.empty(B, dtype=torch.int32, device=dev)
+    lib = lik.lib
+
+    def step(stream):
+        if grad:
+            rc = lib.dsl_loglike_grad(lik.h, C.c_void_p(lam.data_ptr()), B, C.c_void_p(logL.data_ptr()),
+                                      C.c_void_p(g.data_ptr()), None, None, None, C.c_void_p(flags.data_ptr()),
+                                      C.c_void_p(stream))
+        else:
+            rc = lib.dsl_loglike(lik.h, C.c_void_p(lam.data_ptr()), B, C.c_void_p(logL.data_ptr()), None, None,
+                                 None, C.c_void_p(flags.data_ptr()), C.c_void_p(stream))
+        if rc:
+            raise RuntimeError(lib.dsl_last_error().decode())
+
+    st = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.warmup):
+        step(st)
+    torch.cuda.synchronize()
+    print("# warm-up done", file=sys.stderr, flush=True)
+
+    # timed region: K steps, HIP events around each kernel on the launch stream
+    lik.set_option("timing", 1)
+    sweep_ms, setup_ms, comb_ms = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(st)
+        a, b, c = lik.timing()
+        setup_ms.append(a)
+        sweep_ms.append(b)
+        comb_ms.append(c)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lik.set_option("timing", 0)
+    ms_per_step = 1e3 * wall / args.steps
+    value = B * args.steps / wall
+    n_w = cat.n_samp + cat.n_inj
+    flags_h = flags.cpu().numpy()
+    finite = int(np.isfinite(logL.cpu().numpy()).sum())
+
+    # dominant kernel: the sweep
+    sweep_avg = float(np.mean(sweep_ms))
+    F = FLOP_PER_WEIGHT_GRAD if grad else FLOP_PER_WEIGHT_FWD
+    flops = F * n_w * B
+    achieved = flops / (sweep_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "kernel": "sweep_kernel<float,64,%s>" % ("true" if grad else "false"),
+                "kernel_ms": round(sweep_avg, 4),
+                "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                "flop_per_weight": F, "weights_per_launch": n_w * B}
+
+    # one-Lambda-per-launch comparison (same kernels, B = 1, 64 launches)
+    single = None
+    if not args.no_single:
+        lam1 = lam[:1].contiguous()
+        out1 = torch.empty(1, dtype=torch.float64, device=dev)
+        g1 = torch.empty(1, 16, dtype=torch.float64, device=dev)
+
+        def step1(i):
+            src = lam[i:i + 1]
+            lam1.copy_(src)
+            if grad:
+                rc = lib.dsl_loglike_grad(lik.h, C.c_void_p(lam1.data_ptr()), 1, C.c_void_p(out1.data_ptr()),
+                                          C.c_void_p(g1.data_ptr()), None, None, None, None, C.c_void_p(st))
+            else:
+                rc = lib.dsl_loglike(lik.h, C.c_void_p(lam1.data_ptr()), 1, C.c_void_p(out1.data_ptr()), None,
+                                     None, None, None, C.c_void_p(st))
+            if rc:
+                raise RuntimeError(lib.dsl_last_error().decode())
+        for i in range(2):
+            step1(i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(B):
+            step1(i)
+        torch.cuda.synchronize()
+        single_s = time.perf_counter() - t1
+        single = {"ms_per_lambda_single_launch": round(1e3 * single_s / B, 4),
+                  "ms_per_lambda_batched": round(ms_per_step / B, 4),
+                  "speedup_batched_vs_single": round((single_s / B) / (ms_per_step / 1e3 / B), 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cat, lam_np[0], grad)
+
+    res = {
+        "metric": "Lambda-evaluations/sec (log L + grad) on O5-like catalogue" if grad
+        else "Lambda-evaluations/sec (log L) on O5-like catalogue",
+        "value": round(value, 3), "unit": "Lambda-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "O5-like batched (c4): %d events, U[1000,8192] samples/event (%d total), "
+                               "32-2048 pixels/event x %d-node LOS tables (%.2f GB), %d injections, "
+                               "%d Lambda per launch, ln L + d ln L/d Lambda (16 entries)"
+                               % (cat.n_events, cat.n_samp, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B),
+                   "B": B, "precision": "FP32 weights, FP64 sums"},
+        "gsample_weights_per_s": round(n_w * B * args.steps / wall / 1e9, 3),
+        "kernel_ms": {"setup": round(float(np.mean(setup_ms)), 4), "sweep": round(sweep_avg, 4),
+                      "combine": round(float(np.mean(comb_ms)), 4)},
+        "finite_logL": finite, "flags_nonzero": int((flags_h != 0).sum()),
+        "roofline": roofline, "cpu_baseline": cpu, "single_lambda_launches": single,
+    }
+    print(json.dumps(res), flush=True)
+    lik.close()
+
+
+if __name__ == "__main__":
+    main()

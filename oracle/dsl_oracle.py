@@ -157,7 +157,7 @@ def _solve_z(u, Om, z_max, iters=60):
             zn = torch.where(bad, 0.5 * (lo + hi), zn)
             step = torch.abs(zn - z)
             z = zn
-            if bool((step <= 4e-16 * torch.clamp(z, min=1e-300)).all()):
+            if bool((step <= 2e-15 * torch.clamp(z, min=1e-300)).all()):
                 break
         res = torch.abs((1.0 + z) * comoving_integral(z, Om) - u)
         if u.numel():
@@ -246,7 +246,7 @@ def log_Z(m1, L: Lam):
     else:
         Zw = torch.zeros((), dtype=DT)
     in_win = m1 < M
-    up = torch.where(in_win, torch.clamp(m1, min=float(L.mmin)), M + torch.zeros_like(m1))
+    up = torch.where(in_win, torch.clamp(m1, min=float(L.mmin.detach())), M + torch.zeros_like(m1))
     if float(L.delta_m.detach()) > 0.0:
         Zin = _window_integral(torch.where(in_win, up, L.mmin + 0.5 * L.delta_m + torch.zeros_like(up)), L)
     else:

@@ -1,0 +1,667 @@
+// Host side of the library: catalogue validation and upload, the work list,
+// the per-call launch sequence (setup -> sweep -> combine), HIP graph replay,
+// options, the autotuner and the extern "C" entry points of include/dsl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dsl.h"
+#include "dsl_internal.h"
+
+namespace dsl {
+size_t sweep_lds_bytes(int fp32, int GL, bool grad);
+hipError_t launch_pack(int fp32, const double* m1, const double* m2, const double* dl, const double* lnp,
+                       int64_t n, void* out, hipStream_t st);
+hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
+                        void* win_tab, void* win_grad_tab, int* valid, hipStream_t st);
+hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
+hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
+hipError_t init_kernel_attrs();
+}  // namespace dsl
+
+using namespace dsl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hipfail(hipError_t e, const char* what) {
+  return fail(DSL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return hipfail(e_, #x);   \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n && p) return hipSuccess;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      n = 0;
+    }
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+  template <typename X>
+  X* as() const {
+    return reinterpret_cast<X*>(p);
+  }
+};
+
+struct SweepCfg {
+  int GL = 64;          // Lambda per wavefront
+  int64_t chunk = 0;    // target samples per item (0: automatic)
+  int waves = 8;        // wavefronts per workgroup
+  int wg_per_cu = 2;    // workgroups per CU for the persistent grid
+};
+
+struct GraphKey {
+  int B;
+  bool grad;
+  const void* ptrs[8];
+  hipStream_t st;
+  bool operator<(const GraphKey& o) const {
+    if (B != o.B) return B < o.B;
+    if (grad != o.grad) return grad < o.grad;
+    if (st != o.st) return st < o.st;
+    return std::memcmp(ptrs, o.ptrs, sizeof(ptrs)) < 0;
+  }
+};
+
+}  // namespace
+
+struct dsl_handle {
+  int device = 0;
+  int fp32 = 1;
+  int n_cu = 256;
+  int64_t n_events = 0, n_pix = 0, n_samp = 0, n_inj = 0, n_draw = 0, n_rows = 0;
+  int n_z = 0;
+  double z_max = 0;
+  std::vector<int64_t> epo, pso;   // host copies (work-list builder)
+  DevBuf samp, inj, pix_off, pix_row, los, sky, ln_ns;
+  // work list (for the current chunk size)
+  int64_t built_chunk = -1;
+  DevBuf items, order, ev_item_off;
+  int n_items = 0, inj_slot0 = 0, inj_slot1 = 0;
+  // workspace
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part;
+  // options
+  double neff_min = 2.0;
+  int gate_mode = 0;
+  int max_batch = 4096;
+  int lambda_tile = 0;
+  int64_t chunk_opt = 0;
+  int timing = 0;
+  int graph = 1;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool have_timing = false;
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<std::pair<int, int>, SweepCfg> tuned;   // (B, grad) -> configuration
+  ~dsl_handle() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+bool finite_pos(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!(std::isfinite(a[i]) && a[i] > 0)) return false;
+  return true;
+}
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+int validate(const dsl_catalog_desc* d) {
+  if (!d) return fail(DSL_EINVAL, "desc is NULL");
+  if (d->n_events < 1 || !d->event_pix_off) return fail(DSL_EINVAL, "n_events < 1 or event_pix_off NULL");
+  if (d->n_pix < 0 || !d->pix_samp_off || (d->n_pix > 0 && !d->pix_los_row))
+    return fail(DSL_EINVAL, "pixel arrays missing");
+  if (d->n_z < 2 || !(d->z_max > 0) || !std::isfinite(d->z_max)) return fail(DSL_EINVAL, "need n_z >= 2 and z_max > 0");
+  if (d->n_los_rows < 1 || !d->los || !d->sky_z) return fail(DSL_EINVAL, "LOS tables missing");
+  if (d->n_samp < 0 || (d->n_samp > 0 && (!d->m1d || !d->m2d || !d->dl || !d->ln_pi)))
+    return fail(DSL_EINVAL, "sample arrays missing");
+  if (d->n_inj < 1 || !d->inj_m1d || !d->inj_m2d || !d->inj_dl || !d->inj_ln_pdraw)
+    return fail(DSL_EINVAL, "need at least one injection");
+  if (d->n_draw < d->n_inj) return fail(DSL_EINVAL, "n_draw < n_inj");
+  if (d->precision != DSL_PRECISION_FP32 && d->precision != DSL_PRECISION_FP64)
+    return fail(DSL_EINVAL, "precision must be 0 (fp64) or 1 (fp32)");
+  if (d->event_pix_off[0] != 0 || d->event_pix_off[d->n_events] != d->n_pix)
+    return fail(DSL_EINVAL, "event_pix_off must start at 0 and end at n_pix");
+  for (int64_t i = 0; i < d->n_events; ++i)
+    if (d->event_pix_off[i + 1] < d->event_pix_off[i]) return fail(DSL_EINVAL, "event_pix_off not monotone");
+  if (d->pix_samp_off[0] != 0 || d->pix_samp_off[d->n_pix] != d->n_samp)
+    return fail(DSL_EINVAL, "pix_samp_off must start at 0 and end at n_samp");
+  for (int64_t j = 0; j < d->n_pix; ++j) {
+    if (d->pix_samp_off[j + 1] < d->pix_samp_off[j]) return fail(DSL_EINVAL, "pix_samp_off not monotone");
+    if (d->pix_los_row[j] < 0 || d->pix_los_row[j] >= d->n_los_rows)
+      return fail(DSL_EINVAL, "pix_los_row out of range");
+  }
+  if (d->n_pix >= (int64_t)INT32_MAX) return fail(DSL_EINVAL, "too many pixels");
+  if (!finite_pos(d->m1d, d->n_samp) || !finite_pos(d->m2d, d->n_samp) || !finite_pos(d->dl, d->n_samp))
+    return fail(DSL_EINVAL, "sample masses and distances must be finite and > 0");
+  if (!finite_all(d->ln_pi, d->n_samp)) return fail(DSL_EINVAL, "ln_pi must be finite");
+  if (!finite_pos(d->inj_m1d, d->n_inj) || !finite_pos(d->inj_m2d, d->n_inj) || !finite_pos(d->inj_dl, d->n_inj))
+    return fail(DSL_EINVAL, "injection masses and distances must be finite and > 0");
+  if (!finite_all(d->inj_ln_pdraw, d->n_inj)) return fail(DSL_EINVAL, "inj_ln_pdraw must be finite");
+  const int64_t nl = d->n_los_rows * (int64_t)d->n_z;
+  for (int64_t i = 0; i < nl; ++i)
+    if (!std::isfinite(d->los[i]) || d->los[i] < 0) return fail(DSL_EINVAL, "LOS tables must be finite and >= 0");
+  for (int i = 0; i < d->n_z; ++i)
+    if (!std::isfinite(d->sky_z[i]) || d->sky_z[i] < 0) return fail(DSL_EINVAL, "sky_z must be finite and >= 0");
+  return DSL_OK;
+}
+
+int upload(DevBuf& b, const void* src, size_t bytes) {
+  hipError_t e = b.ensure(bytes);
+  if (e != hipSuccess) return fail(DSL_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  return DSL_OK;
+}
+
+int pack_samples(dsl_handle* h, DevBuf& out, const double* m1, const double* m2, const double* dl,
+                 const double* lnp, int64_t n) {
+  const size_t rec = h->fp32 ? sizeof(Samp<float>) : sizeof(Samp<double>);
+  hipError_t e = out.ensure(rec * (size_t)std::max<int64_t>(n, 1));
+  if (e != hipSuccess) return fail(DSL_ENOMEM, std::string("hipMalloc samples: ") + hipGetErrorString(e));
+  // stream the raw arrays through a staging buffer in slices
+  const int64_t slice = 1 << 22;
+  DevBuf stage;
+  e = stage.ensure(4 * sizeof(double) * (size_t)std::min<int64_t>(std::max<int64_t>(n, 1), slice));
+  if (e != hipSuccess) return fail(DSL_ENOMEM, "hipMalloc staging");
+  for (int64_t s = 0; s < n; s += slice) {
+    const int64_t m = std::min(slice, n - s);
+    double* st = stage.as<double>();
+    HIPCHK(hipMemcpy(st, m1 + s, m * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(st + m, m2 + s, m * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(st + 2 * m, dl + s, m * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(st + 3 * m, lnp + s, m * sizeof(double), hipMemcpyHostToDevice));
+    char* dst = out.as<char>() + rec * (size_t)s;
+    HIPCHK(launch_pack(h->fp32, st, st + m, st + 2 * m, st + 3 * m, m, dst, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+  }
+  return DSL_OK;
+}
+
+int64_t auto_chunk(const dsl_handle* h) {
+  const int64_t total = h->n_samp + h->n_inj;
+  int64_t c = total / ((int64_t)h->n_cu * 64);
+  return std::max<int64_t>(64, std::min<int64_t>(16384, c));
+}
+
+// Work list: runs of whole pixels of one event (about `chunk` samples each; a
+// larger pixel forms its own item) and runs of `chunk` injections.  Slots are
+// in event order; the processing order puts the largest items first.
+int build_items(dsl_handle* h, int64_t chunk) {
+  if (chunk == h->built_chunk) return DSL_OK;
+  std::vector<WorkItem> it;
+  std::vector<int32_t> ev_off(h->n_events + 1, 0);
+  for (int64_t e = 0; e < h->n_events; ++e) {
+    ev_off[e] = (int32_t)it.size();
+    const int64_t p0 = h->epo[e], p1 = h->epo[e + 1];
+    int64_t a = p0;
+    while (a < p1) {
+      int64_t b = a + 1;
+      int64_t n = h->pso[b] - h->pso[a];
+      while (b < p1 && n + (h->pso[b + 1] - h->pso[b]) <= chunk) {
+        n += h->pso[b + 1] - h->pso[b];
+        ++b;
+      }
+      WorkItem w;
+      w.event = (int32_t)e;
+      w.pix0 = (int32_t)a;
+      w.pix1 = (int32_t)b;
+      w.slot = (int32_t)it.size();
+      w.s0 = h->pso[a];
+      w.s1 = h->pso[b];
+      it.push_back(w);
+      a = b;
+    }
+  }
+  ev_off[h->n_events] = (int32_t)it.size();
+  const int inj0 = (int)it.size();
+  for (int64_t s = 0; s < h->n_inj; s += chunk) {
+    WorkItem w;
+    w.event = -1;
+    w.pix0 = w.pix1 = 0;
+    w.slot = (int32_t)it.size();
+    w.s0 = s;
+    w.s1 = std::min(h->n_inj, s + chunk);
+    it.push_back(w);
+  }
+  std::vector<int32_t> ord(it.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int32_t)i;
+  auto cost = [&](int32_t i) { return (it[i].s1 - it[i].s0) + 4 * (int64_t)(it[i].pix1 - it[i].pix0); };
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+  int rc;
+  if ((rc = upload(h->items, it.data(), it.size() * sizeof(WorkItem)))) return rc;
+  if ((rc = upload(h->order, ord.data(), ord.size() * sizeof(int32_t)))) return rc;
+  if ((rc = upload(h->ev_item_off, ev_off.data(), ev_off.size() * sizeof(int32_t)))) return rc;
+  h->n_items = (int)it.size();
+  h->inj_slot0 = inj0;
+  h->inj_slot1 = (int)it.size();
+  h->built_chunk = chunk;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  return DSL_OK;
+}
+
+int default_gl(const dsl_handle* h, int B) {
+  if (!h->fp32) return B >= 4 ? 4 : 1;
+  if (B >= 48) return 64;
+  if (B >= 12) return 16;
+  if (B >= 3) return 4;
+  return 1;
+}
+
+SweepCfg config_for(dsl_handle* h, int B, bool grad) {
+  auto it = h->tuned.find({B, grad ? 1 : 0});
+  SweepCfg c;
+  if (it != h->tuned.end()) c = it->second;
+  else c.GL = default_gl(h, B);
+  if (h->lambda_tile) c.GL = h->lambda_tile;
+  if (!h->fp32 && c.GL > 4) c.GL = 4;
+  if (h->chunk_opt) c.chunk = h->chunk_opt;
+  if (c.chunk <= 0) c.chunk = auto_chunk(h);
+  return c;
+}
+
+int ensure_workspace(dsl_handle* h, int B, bool grad) {
+  const int NU = h->fp32 ? NU_F32 : NU_F64, NW = h->fp32 ? NW_F32 : NW_F64;
+  const size_t t1 = h->fp32 ? sizeof(float) : sizeof(double);
+  const size_t lc = h->fp32 ? sizeof(LamC<float>) : sizeof(LamC<double>);
+  hipError_t e;
+  if ((e = h->lamc.ensure(lc * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (lamc)");
+  if ((e = h->cos_tab.ensure(2 * t1 * (NU + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (cos)");
+  if ((e = h->win_tab.ensure(2 * t1 * (NW + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (win)");
+  const int NWG = h->fp32 ? NWG_F32 : NWG_F64;
+  if ((e = h->wg_tab.ensure(6 * t1 * (NWG + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (wg)");
+  if ((e = h->valid.ensure(sizeof(int) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (valid)");
+  const size_t nf = grad ? NF_GRAD : NF_FWD;
+  if ((e = h->part.ensure(sizeof(double) * nf * (size_t)B * std::max(h->n_items, 1))) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (partials)");
+  return DSL_OK;
+}
+
+struct CallOut {
+  double* logL;
+  double* grad;
+  double* logL_event;
+  double* neff_event;
+  double* neff_sel;
+  uint32_t* flags;
+};
+
+// Enqueue setup -> sweep -> combine on st (no synchronisation).
+int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& o, const SweepCfg& cfg,
+            hipStream_t st, bool timed) {
+  if (timed) HIPCHK(hipEventRecord(h->ev[0], st));
+  HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, h->lamc.p, h->cos_tab.p, h->win_tab.p,
+                      grad ? h->wg_tab.p : nullptr, h->valid.as<int>(), st));
+  if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
+  SweepArgs a;
+  a.samp = h->samp.p;
+  a.inj = h->inj.p;
+  a.pix_off = h->pix_off.as<int64_t>();
+  a.pix_row = h->pix_row.as<int32_t>();
+  a.los = h->los.as<float>();
+  a.sky = h->sky.as<float>();
+  a.n_z = h->n_z;
+  a.z_max = h->z_max;
+  a.items = h->items.as<WorkItem>();
+  a.order = h->order.as<int32_t>();
+  a.n_items = h->n_items;
+  a.lamc = h->lamc.p;
+  a.cos_tab = h->cos_tab.p;
+  a.win_tab = h->win_tab.p;
+  a.win_grad_tab = h->wg_tab.p;
+  a.B = B;
+  a.neff_min = h->neff_min;
+  a.gate_mode = h->gate_mode;
+  a.part = h->part.as<double>();
+  const int n_tiles = (B + cfg.GL - 1) / cfg.GL;
+  const int waves = cfg.waves;
+  int grid_x = std::max(1, (h->n_cu * cfg.wg_per_cu + n_tiles - 1) / n_tiles);
+  grid_x = std::min(grid_x, std::max(1, (h->n_items + waves - 1) / waves));
+  HIPCHK(launch_sweep(h->fp32, cfg.GL, grad, a, grid_x, 64 * waves, st));
+  if (timed) HIPCHK(hipEventRecord(h->ev[2], st));
+  CombineArgs c;
+  c.part = h->part.as<double>();
+  c.nf = grad ? NF_GRAD : NF_FWD;
+  c.B = B;
+  c.n_events = (int32_t)h->n_events;
+  c.ev_item_off = h->ev_item_off.as<int32_t>();
+  c.inj_slot0 = h->inj_slot0;
+  c.inj_slot1 = h->inj_slot1;
+  c.ln_ns = h->ln_ns.as<double>();
+  c.ln_ndraw = std::log((double)h->n_draw);
+  c.neff_min = h->neff_min;
+  c.gate_mode = h->gate_mode;
+  c.valid = h->valid.as<int>();
+  c.logL = o.logL;
+  c.logL_event = o.logL_event;
+  c.neff_event = o.neff_event;
+  c.neff_sel = o.neff_sel;
+  c.flags = o.flags;
+  c.grad = o.grad;
+  HIPCHK(launch_combine(grad, c, st));
+  if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
+  return DSL_OK;
+}
+
+int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& o, hipStream_t st) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  if (!d_lambda || !o.logL || (grad && !o.grad)) return fail(DSL_EINVAL, "NULL device pointer");
+  if (B < 1 || B > h->max_batch) return fail(DSL_EINVAL, "B out of range [1, max_batch]");
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != h->device) return fail(DSL_ESTATE, "current device differs from the handle's device");
+  const SweepCfg cfg = config_for(h, B, grad);
+  int rc;
+  if ((rc = build_items(h, cfg.chunk))) return rc;
+  if ((rc = ensure_workspace(h, B, grad))) return rc;
+  if (h->timing) {
+    h->have_timing = true;
+    return enqueue(h, d_lambda, B, grad, o, cfg, st, true);
+  }
+  if (!h->graph) return enqueue(h, d_lambda, B, grad, o, cfg, st, false);
+  GraphKey k{};
+  k.B = B;
+  k.grad = grad;
+  k.st = st;
+  const void* ptrs[8] = {d_lambda, o.logL, o.grad, o.logL_event, o.neff_event, o.neff_sel, o.flags,
+                         (const void*)(intptr_t)(cfg.GL * 1000003 + cfg.chunk)};
+  std::memcpy(k.ptrs, ptrs, sizeof(ptrs));
+  auto it = h->graphs.find(k);
+  if (it == h->graphs.end()) {
+    if (h->graphs.size() >= 16) {
+      for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+      h->graphs.clear();
+    }
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(h, d_lambda, B, grad, o, cfg, h->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hipfail(e, "hipGraphInstantiate");
+    it = h->graphs.emplace(k, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, st));
+  return DSL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dsl_last_error(void) { return g_err.c_str(); }
+
+const char* dsl_version(void) { return "dsl 0.1 (gfx950)"; }
+
+int dsl_create(const dsl_catalog_desc* d, dsl_handle** out) {
+  if (!out) return fail(DSL_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc) return rc;
+  std::unique_ptr<dsl_handle> h(new (std::nothrow) dsl_handle());
+  if (!h) return fail(DSL_ENOMEM, "host allocation");
+  HIPCHK(hipGetDevice(&h->device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, h->device));
+  h->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  h->fp32 = d->precision == DSL_PRECISION_FP32;
+  h->n_events = d->n_events;
+  h->n_pix = d->n_pix;
+  h->n_samp = d->n_samp;
+  h->n_inj = d->n_inj;
+  h->n_draw = d->n_draw;
+  h->n_rows = d->n_los_rows;
+  h->n_z = d->n_z;
+  h->z_max = d->z_max;
+  h->epo.assign(d->event_pix_off, d->event_pix_off + d->n_events + 1);
+  h->pso.assign(d->pix_samp_off, d->pix_samp_off + d->n_pix + 1);
+  std::vector<double> ln_ns(d->n_events);
+  for (int64_t e = 0; e < d->n_events; ++e) {
+    const int64_t ns = h->pso[h->epo[e + 1]] - h->pso[h->epo[e]];
+    ln_ns[e] = ns > 0 ? std::log((double)ns) : 0.0;
+  }
+  if ((rc = upload(h->pix_off, d->pix_samp_off, sizeof(int64_t) * (d->n_pix + 1)))) return rc;
+  if ((rc = upload(h->pix_row, d->pix_los_row, sizeof(int32_t) * std::max<int64_t>(d->n_pix, 1)))) return rc;
+  if ((rc = upload(h->los, d->los, sizeof(float) * d->n_los_rows * (size_t)d->n_z))) return rc;
+  if ((rc = upload(h->sky, d->sky_z, sizeof(float) * d->n_z))) return rc;
+  if ((rc = upload(h->ln_ns, ln_ns.data(), sizeof(double) * ln_ns.size()))) return rc;
+  if ((rc = pack_samples(h.get(), h->samp, d->m1d, d->m2d, d->dl, d->ln_pi, d->n_samp))) return rc;
+  if ((rc = pack_samples(h.get(), h->inj, d->inj_m1d, d->inj_m2d, d->inj_dl, d->inj_ln_pdraw, d->n_inj))) return rc;
+  for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHK(init_kernel_attrs());
+  *out = h.release();
+  return DSL_OK;
+}
+
+void dsl_destroy(dsl_handle* h) { delete h; }
+
+int dsl_set_option(dsl_handle* h, const char* key, double v) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  if (!key) return fail(DSL_EINVAL, "key is NULL");
+  const std::string k(key);
+  if (!std::isfinite(v)) return fail(DSL_EINVAL, "value must be finite");
+  if (k == "neff_min") {
+    if (v < 0) return fail(DSL_EINVAL, "neff_min must be >= 0");
+    h->neff_min = v;
+  } else if (k == "gate_mode") {
+    if (v != 0 && v != 1 && v != 2) return fail(DSL_EINVAL, "gate_mode must be 0, 1 or 2");
+    h->gate_mode = (int)v;
+  } else if (k == "max_batch") {
+    if (v < 1 || v > (1 << 20)) return fail(DSL_EINVAL, "max_batch out of range");
+    h->max_batch = (int)v;
+  } else if (k == "lambda_tile") {
+    const int g = (int)v;
+    if (v != g || !(g == 0 || g == 1 || g == 4 || g == 16 || g == 64)) return fail(DSL_EINVAL, "lambda_tile must be 0, 1, 4, 16 or 64");
+    if (!h->fp32 && g > 4) return fail(DSL_EINVAL, "fp64 supports lambda_tile 0, 1 or 4");
+    h->lambda_tile = g;
+  } else if (k == "chunk") {
+    if (v < 0 || v > (1 << 24)) return fail(DSL_EINVAL, "chunk out of range");
+    h->chunk_opt = (int64_t)v;
+  } else if (k == "timing") {
+    h->timing = v != 0;
+  } else if (k == "graph") {
+    h->graph = v != 0;
+  } else {
+    return fail(DSL_EINVAL, "unknown option '" + k + "'");
+  }
+  // graphs bake in option values
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  return DSL_OK;
+}
+
+int dsl_get_info(dsl_handle* h, const char* key, double* v) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  if (!key || !v) return fail(DSL_EINVAL, "NULL argument");
+  const std::string k(key);
+  if (k == "n_events") *v = (double)h->n_events;
+  else if (k == "n_pix") *v = (double)h->n_pix;
+  else if (k == "n_samp") *v = (double)h->n_samp;
+  else if (k == "n_inj") *v = (double)h->n_inj;
+  else if (k == "n_draw") *v = (double)h->n_draw;
+  else if (k == "n_z") *v = (double)h->n_z;
+  else if (k == "n_items") *v = (double)h->n_items;
+  else if (k == "precision") *v = h->fp32 ? DSL_PRECISION_FP32 : DSL_PRECISION_FP64;
+  else if (k == "neff_min") *v = h->neff_min;
+  else if (k == "gate_mode") *v = h->gate_mode;
+  else if (k == "max_batch") *v = h->max_batch;
+  else if (k == "lambda_tile") *v = h->lambda_tile;
+  else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : auto_chunk(h));
+  else if (k == "n_cu") *v = h->n_cu;
+  else if (k == "device_bytes") {
+    *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
+                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n);
+  } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
+  return DSL_OK;
+}
+
+int dsl_loglike(dsl_handle* h, const double* d_lambda, int B, double* d_logL, double* d_logL_event,
+                double* d_neff_event, double* d_neff_sel, uint32_t* d_flags, void* stream) {
+  CallOut o{d_logL, nullptr, d_logL_event, d_neff_event, d_neff_sel, d_flags};
+  return run(h, d_lambda, B, false, o, (hipStream_t)stream);
+}
+
+int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_logL, double* d_grad,
+                     double* d_logL_event, double* d_neff_event, double* d_neff_sel, uint32_t* d_flags,
+                     void* stream) {
+  CallOut o{d_logL, d_grad, d_logL_event, d_neff_event, d_neff_sel, d_flags};
+  return run(h, d_lambda, B, true, o, (hipStream_t)stream);
+}
+
+int dsl_get_timing(dsl_handle* h, float* ms_setup, float* ms_sweep, float* ms_combine) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  if (!h->have_timing) return fail(DSL_ESTATE, "no timed call yet (set option 'timing' to 1)");
+  HIPCHK(hipEventSynchronize(h->ev[3]));
+  float a = 0, b = 0, c = 0;
+  HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+  HIPCHK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+  HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
+  if (ms_setup) *ms_setup = a;
+  if (ms_sweep) *ms_sweep = b;
+  if (ms_combine) *ms_combine = c;
+  return DSL_OK;
+}
+
+int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  if (B < 1 || B > h->max_batch) return fail(DSL_EINVAL, "B out of range");
+  const bool grad = with_grad != 0;
+  char devname[64] = {0};
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->device));
+    std::snprintf(devname, sizeof(devname), "%s", prop.gcnArchName);
+  }
+  std::ostringstream keyss;
+  keyss << devname << "|fp32=" << h->fp32 << "|grad=" << grad << "|B=" << B << "|samp=" << h->n_samp
+        << "|inj=" << h->n_inj << "|pix=" << h->n_pix << "|ev=" << h->n_events;
+  const std::string key = keyss.str();
+  // cache lookup: one line per entry, "key GL chunk waves wg_per_cu"
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      SweepCfg c;
+      if (ls >> k >> c.GL >> c.chunk >> c.waves >> c.wg_per_cu && k == key) {
+        h->tuned[{B, grad ? 1 : 0}] = c;
+        return DSL_OK;
+      }
+    }
+  }
+  // candidates
+  std::vector<int> gls = h->fp32 ? std::vector<int>{1, 4, 16, 64} : std::vector<int>{1, 4};
+  const int64_t base = auto_chunk(h);
+  std::vector<int64_t> chunks = {std::max<int64_t>(64, base / 4), base, std::min<int64_t>(65536, base * 4)};
+  // scratch Lambda batch: the prior's centre replicated (valid everywhere)
+  std::vector<double> lam(16 * (size_t)B);
+  const double centre[16] = {70, 0.3, 2.9, 1.0, 4.6, 86.3, 4.8, 9.7, 0.7, 30.7, 6.3, 0.4, 0.8, 3.3, 2.9, 2.5};
+  for (int b = 0; b < B; ++b)
+    for (int p = 0; p < 16; ++p) lam[16 * b + p] = centre[p];
+  DevBuf dl, dout, dg;
+  if (dl.ensure(sizeof(double) * 16 * B) || dout.ensure(sizeof(double) * B) || dg.ensure(sizeof(double) * 16 * B))
+    return fail(DSL_ENOMEM, "autotune scratch");
+  HIPCHK(hipMemcpy(dl.p, lam.data(), sizeof(double) * 16 * B, hipMemcpyHostToDevice));
+  const int saved_tile = h->lambda_tile;
+  const int64_t saved_chunk = h->chunk_opt;
+  const int saved_graph = h->graph, saved_timing = h->timing;
+  h->lambda_tile = 0;
+  h->chunk_opt = 0;
+  h->graph = 0;
+  h->timing = 0;
+  SweepCfg best;
+  double best_ms = 1e300;
+  int rc = DSL_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int gl : gls) {
+    if (gl > 1 && B < gl / 4) continue;   // mostly idle lanes
+    for (int64_t ch : chunks) {
+      SweepCfg c;
+      c.GL = gl;
+      c.chunk = ch;
+      h->tuned[{B, grad ? 1 : 0}] = c;
+      CallOut o{dout.as<double>(), grad ? dg.as<double>() : nullptr, nullptr, nullptr, nullptr, nullptr};
+      if ((rc = run(h, dl.as<double>(), B, grad, o, nullptr))) break;   // warm-up (and build)
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipEventRecord(e0, nullptr));
+      const int reps = 3;
+      for (int r = 0; r < reps && !rc; ++r) rc = run(h, dl.as<double>(), B, grad, o, nullptr);
+      HIPCHK(hipEventRecord(e1, nullptr));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (rc) break;
+      if (ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best = c;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->lambda_tile = saved_tile;
+  h->chunk_opt = saved_chunk;
+  h->graph = saved_graph;
+  h->timing = saved_timing;
+  if (rc) {
+    h->tuned.erase({B, grad ? 1 : 0});
+    return rc;
+  }
+  h->tuned[{B, grad ? 1 : 0}] = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << key << " " << best.GL << " " << best.chunk << " " << best.waves << " " << best.wg_per_cu << "\n";
+  }
+  return DSL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal layouts shared by the host side (dsl_abi.cpp) and the kernels
+// (dsl_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsl {
+
+constexpr double C_KMS = 299792.458;
+constexpr double LN2 = 0.69314718055994530942;
+constexpr double LOG2E = 1.44269504088896340736;
+
+// Hermite segments of the per-Lambda tables.  z(u) is tabulated as z/u against
+// v = sqrt(1 + 4u) (see setup kernel); the smoothing-window table as
+// rho = Z(m1) / (S(m1) m1^(beta+1)) against t = (m1 - m_min) / delta_m.
+constexpr int NU_F32 = 64;
+constexpr int NW_F32 = 64;
+constexpr int NU_F64 = 1024;
+constexpr int NW_F64 = 256;
+// The adjoint's window-derivative tables use every second node (Hermite, with
+// tangents from 5-point differences on the full grid).
+constexpr int NWG_F32 = NW_F32 / 2;
+constexpr int NWG_F64 = NW_F64 / 2;
+
+constexpr int R_SENTINEL = -(1 << 20);   // "no weight yet" binary exponent
+constexpr int RESCALE_MARGIN = 60;        // new max exponent that forces a rescale
+
+// Per-Lambda constants of the sweep (one copy per precision).
+template <typename T>
+struct LamC {
+  T H0;            // u = (d_L / c) * H0
+  T u_max;         // (1+z_max) I(z_max): larger u is outside the support
+  T inv_hv;        // table segments per unit of v = sqrt(1 + 4u)
+  T Om, OL;        // Omega_m, 1 - Omega_m
+  T c0;            // log2(H0 / c)
+  T alpha, beta, mmin, mmax, dm, inv_dm;
+  T cP, cL, cH;    // log2 of mixture weight x component normalisation
+  T muL, kL, muH, kH;   // peak centres, -log2(e) / (2 sigma^2)
+  T s, inv_s, lM, zw;   // beta+1, 1/(beta+1), log2(m_min+delta_m), Z_w / M^s
+  T gm3, gk, Lp;   // gamma - 3, gamma + kappa, log2(1 + z_p)
+  // --- gradient constants (natural-log derivatives of the normalisations)
+  T dbP_alpha, dbP_mmin, dbP_mmax;            // d ln b_P
+  T dbL_mu, dbL_sig, dbL_mmin, dbL_mmax;       // d ln b_L (b_L = 1/(sig sqrt(2pi) dPhi))
+  T dbH_mu, dbH_sig, dbH_mmin, dbH_mmax;
+  T sigL, sigH;                               // sigma_low, sigma_high
+  T lg, ll;                                   // lambda_g, lambda_low
+  T zw_beta, zw_mmin, zw_dm;                  // window integrals of d/d(beta, m_min, dm) of m^beta S, / M^s
+  T gamma, kappa, inv_opzp;                   // gamma, kappa, 1/(1+z_p)
+  int valid;
+  int pad_;
+};
+
+// Number of window-derivative tables used by the adjoint (beta, m_min, delta_m).
+constexpr int N_WIN_GRAD = 3;
+
+// Work item: a run of whole pixels of one event, or a run of injections.
+struct WorkItem {
+  int32_t event;     // >= 0: event index; -1: injection chunk
+  int32_t pix0, pix1;
+  int32_t slot;      // row of the partial-result buffer
+  int64_t s0, s1;    // sample (or injection) range
+};
+
+// Packed sample (the sweep's input record), precision T.
+template <typename T>
+struct Samp {
+  T m1d, m2d;      // detector-frame masses
+  T lm1d, lm2d;    // log2 of them
+  T dlc;           // d_L / c  [Mpc s/km]
+  T nlp;           // -ln(prior) / ln 2
+  T lq;            // log2(m2d / m1d)
+  T pad;
+};
+
+// Fields of one partial result (per work item and Lambda).
+constexpr int NF_FWD = 4;              // R, S1, S2, n_pass
+constexpr int NF_GRAD = 4 + 16;        // + sum w * dln w / dLambda
+
+struct SweepArgs {
+  const void* samp;          // Samp<T>[n_samp]
+  const void* inj;           // Samp<T>[n_inj]
+  const int64_t* pix_off;    // [n_pix + 1]
+  const int32_t* pix_row;    // [n_pix]
+  const float* los;          // [rows][n_z]
+  const float* sky;          // [n_z]
+  int32_t n_z;
+  double z_max;
+  const WorkItem* items;     // in slot order
+  const int32_t* order;      // processing order of items
+  int32_t n_items;
+  const void* lamc;          // LamC<T>[B]
+  const void* cos_tab;       // [B][NU+1] of T2
+  const void* win_tab;       // [B][NW+1] of T2
+  const void* win_grad_tab;  // [B][N_WIN_GRAD][NWG+1] of T2 (adjoint only)
+  int32_t B;
+  double neff_min;
+  int32_t gate_mode;
+  double* part;              // [n_items][NF][B]
+};
+
+struct CombineArgs {
+  const double* part;
+  int32_t nf;                // NF_FWD or NF_GRAD
+  int32_t B;
+  int32_t n_events;
+  const int32_t* ev_item_off;   // [n_events + 1] slot ranges
+  int32_t inj_slot0, inj_slot1;
+  const double* ln_ns;          // [n_events] ln N_s,i
+  double ln_ndraw;
+  double neff_min;
+  int32_t gate_mode;
+  const int* valid;             // [B] (from setup)
+  double* logL;                 // [B]
+  double* logL_event;           // [B][n_events] or null
+  double* neff_event;           // [B][n_events] or null
+  double* neff_sel;             // [B] or null
+  uint32_t* flags;              // [B] or null
+  double* grad;                 // [B][16] or null
+};
+
+}  // namespace dsl

@@ -1,0 +1,1040 @@
+// HIP kernels (gfx950) of the dark-siren population log-likelihood.
+//
+//   setup_kernel    one workgroup per hyperparameter point: FP64 cosmology and
+//                   mass-model constants, the z(d_L) inverse table and the
+//                   smoothing-window tables (Eq. 1 and the MultiPeak model).
+//   sweep_kernel    persistent sweep over work items (runs of whole pixels of
+//                   one event, or runs of injections): per-sample weights of
+//                   Eq. (7), FP64 per-pixel sums, the Eq. (8) gate, per-item
+//                   partial sums; optionally the adjoint (d ln w / d Lambda).
+//   combine_kernel  one workgroup per point: per-event ln L_i, N_eff,i, the
+//                   selection term and ln L (Eqs. 3-5), in a fixed order.
+//
+// Weights are carried as w = 2^n * lin (integer n, FP32 or FP64 lin) so every
+// factor that can over- or underflow (prior, power laws, smoothing tails) is
+// added into the binary exponent, and FP64 sums are rescaled by exact powers
+// of two: the log-sum-exp needs no transcendental per merge.
+#include "dsl_internal.h"
+
+namespace dsl {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+template <typename T> struct Mth;
+template <> struct Mth<float> {
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float fl(float x) { return __builtin_floorf(x); }
+};
+template <> struct Mth<double> {
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double fl(double x) { return ::floor(x); }
+};
+
+template <typename T> struct Tab { static constexpr int NU = NU_F32, NW = NW_F32, NWG = NWG_F32; };
+template <> struct Tab<double> { static constexpr int NU = NU_F64, NW = NW_F64, NWG = NWG_F64; };
+
+// ---------------------------------------------------------------------------
+// FP64 helpers of the setup kernel
+// ---------------------------------------------------------------------------
+__device__ inline double E_of(double z, double Om) {
+  const double x = 1.0 + z;
+  return sqrt(Om * x * x * x + (1.0 - Om));
+}
+
+// 8-point Gauss-Legendre nodes/weights on [-1, 1].
+__constant__ double GL8_X[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                                -0.1834346424956498, 0.1834346424956498, 0.5255324099163290,
+                                0.7966664774136267, 0.9602898564975363};
+__constant__ double GL8_W[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                                0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                                0.2223810344533745, 0.1012285362903763};
+
+// I(z) = int_0^z dz'/E(z') by composite 8-point Gauss-Legendre (8 panels).
+__device__ double comoving_I(double z, double Om) {
+  const int P = 8;
+  const double h = z / P;
+  double acc = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const double c = (p + 0.5) * h;
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) s += GL8_W[k] / E_of(c + 0.5 * h * GL8_X[k], Om);
+    acc += 0.5 * h * s;
+  }
+  return acc;
+}
+
+// Smoothing window S(m) and its logarithmic derivatives (x = m - m_min).
+struct SmoothD {
+  double S, omS;   // S and 1 - S
+  double dlnS_dm, dlnS_ddm;
+};
+__device__ inline SmoothD smooth_d(double x, double dm) {
+  SmoothD r;
+  if (x <= 0.0) { r.S = 0.0; r.omS = 1.0; r.dlnS_dm = 0.0; r.dlnS_ddm = 0.0; return r; }
+  if (x >= dm) { r.S = 1.0; r.omS = 0.0; r.dlnS_dm = 0.0; r.dlnS_ddm = 0.0; return r; }
+  const double y = dm / x + dm / (x - dm);
+  if (y > 0) { const double e = exp(-y); r.S = e / (1.0 + e); r.omS = 1.0 / (1.0 + e); }
+  else { const double e = exp(y); r.S = 1.0 / (1.0 + e); r.omS = e / (1.0 + e); }
+  const double dy_dm = -dm / (x * x) - dm / ((x - dm) * (x - dm));
+  const double dy_ddm = 1.0 / x + x / ((x - dm) * (x - dm));
+  r.dlnS_dm = -r.omS * dy_dm;
+  r.dlnS_ddm = -r.omS * dy_ddm;
+  return r;
+}
+
+__device__ inline double log_dPhi(double mu, double sig, double lo, double hi) {
+  // ln(Phi((hi-mu)/sig) - Phi((lo-mu)/sig)), stable in both tails.
+  const double a = (lo - mu) / sig, b = (hi - mu) / sig;
+  const double r2 = 0.70710678118654752440;
+  double d;
+  if (a > 0) d = 0.5 * (erfc(a * r2) - erfc(b * r2));
+  else if (b < 0) d = 0.5 * (erfc(-b * r2) - erfc(-a * r2));
+  else d = 1.0 - 0.5 * erfc(-a * r2) - 0.5 * erfc(b * r2);
+  return log(d);
+}
+
+// ---------------------------------------------------------------------------
+// setup: per-Lambda constants and tables (FP64), one workgroup per point
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ lam, int B, double z_max,
+                                                    LamC<T>* __restrict__ lamc,
+                                                    typename V2<T>::t* __restrict__ cos_tab,
+                                                    typename V2<T>::t* __restrict__ win_tab,
+                                                    typename V2<T>::t* __restrict__ win_grad_tab,
+                                                    int* __restrict__ valid_out) {
+  using T2 = typename V2<T>::t;
+  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW, NWG = Tab<T>::NWG;
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const double* L = lam + 16 * b;
+  const double H0 = L[0], Om = L[1], alpha = L[2], beta = L[3], mmin = L[4], mmax = L[5], dm = L[6];
+  const double muL = L[7], sL = L[8], muH = L[9], sH = L[10], lg = L[11], ll = L[12];
+  const double gam = L[13], kap = L[14], zp = L[15];
+  bool ok = true;
+  for (int i = 0; i < 16; ++i) ok = ok && isfinite(L[i]);
+  ok = ok && H0 > 0 && Om >= 0 && Om <= 1 && mmin > 0 && mmin < mmax && dm >= 0 && sL > 0 && sH > 0 &&
+       lg >= 0 && lg <= 1 && ll >= 0 && ll <= 1 && zp > -1;
+  __shared__ double zw_s[4];
+  __shared__ double cum[NW + 1];
+  __shared__ double cumg[3][NW + 1];
+  __shared__ double gfine[3][NW + 1];
+  const int tid = threadIdx.x;
+  const double M = mmin + dm;
+  const double s = beta + 1.0;
+
+  // --- inverse distance table: y(v) = z/u at v_k = 1 + k h_v, u = (v^2-1)/4.
+  const double umax = ok ? (1.0 + z_max) * comoving_I(z_max, Om) : 1.0;
+  const double vmax = sqrt(1.0 + 4.0 * umax);
+  const double hv = (vmax - 1.0) / NU;
+  for (int k = tid; k <= NU; k += blockDim.x) {
+    double y = 1.0, dy = -(1.0 - 0.75 * Om) * 0.5;  // limits at u = 0
+    if (k > 0 && ok) {
+      const double dv = k * hv;
+      const double u = dv * (2.0 + dv) * 0.25;
+      const double v = 1.0 + dv;
+      double z = 2.0 * u / (1.0 + v), lo = 0.0, hi = z_max * 1.0000001;
+      for (int it = 0; it < 40; ++it) {
+        const double I = comoving_I(z, Om);
+        const double f = (1.0 + z) * I - u;
+        if (f > 0) hi = z; else lo = z;
+        double zn = z - f / (I + (1.0 + z) / E_of(z, Om));
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+        const bool done = fabs(zn - z) <= 1e-14 * z;
+        z = zn;
+        if (done) break;
+      }
+      const double I = comoving_I(z, Om);
+      const double zp_u = 1.0 / (I + (1.0 + z) / E_of(z, Om));
+      y = z / u;
+      dy = (zp_u * u - z) / (u * u) * (0.5 * v);
+    }
+    T2 e;
+    e.x = (T)y;
+    e.y = (T)(dy * hv);
+    cos_tab[(size_t)b * (NU + 1) + k] = e;
+  }
+
+  // --- smoothing-window integrals on NW panels (Gauss-Legendre 8 x 2 per panel)
+  // panel integrals of m^beta S, and of m^beta d S/d(beta, m_min, dm) for the adjoint.
+  const bool win = ok && dm > 0;
+  for (int j = tid; j < NW; j += blockDim.x) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if (win) {
+      const double ta = (double)j / NW, h = 1.0 / NW;
+      for (int half = 0; half < 2; ++half) {
+        const double c = ta + (half + 0.5) * 0.5 * h;
+        for (int q = 0; q < 8; ++q) {
+          const double t = c + 0.25 * h * GL8_X[q];
+          const double m = mmin + dm * t;
+          const SmoothD sd = smooth_d(m - mmin, dm);
+          const double wq = GL8_W[q] * 0.25 * h * dm;
+          const double mb = exp(beta * log(m));
+          a0 += wq * mb * sd.S;
+          a1 += wq * mb * log(m) * sd.S;
+          a2 += wq * mb * sd.S * (-sd.dlnS_dm);    // dS/dm_min = -dS/dm
+          a3 += wq * mb * sd.S * sd.dlnS_ddm;
+        }
+      }
+    }
+    cum[j + 1] = a0;
+    cumg[0][j + 1] = a1;
+    cumg[1][j + 1] = a2;
+    cumg[2][j + 1] = a3;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cum[0] = 0;
+    cumg[0][0] = cumg[1][0] = cumg[2][0] = 0;
+    for (int j = 1; j <= NW; ++j) {
+      cum[j] += cum[j - 1];
+      cumg[0][j] += cumg[0][j - 1];
+      cumg[1][j] += cumg[1][j - 1];
+      cumg[2][j] += cumg[2][j - 1];
+    }
+    const double Ms = exp(s * log(M));
+    zw_s[0] = win ? cum[NW] / Ms : 0.0;
+    zw_s[1] = win ? cumg[0][NW] / Ms : 0.0;
+    zw_s[2] = win ? cumg[1][NW] / Ms : 0.0;
+    zw_s[3] = win ? cumg[2][NW] / Ms : 0.0;
+  }
+  __syncthreads();
+  // rho(t) = Z / (S m^s) and its t-derivative; gradient tables d rho / d(beta, m_min, dm).
+  for (int j = tid; j <= NW; j += blockDim.x) {
+    double rho = 0, drho = 0, g[3] = {0, 0, 0};
+    if (win && j > 0) {
+      const double t = (double)j / NW;
+      const double m = mmin + dm * t;
+      const SmoothD sd = smooth_d(m - mmin, dm);
+      const double ms = exp(s * log(m));
+      const double Sd = (j == NW) ? 1.0 : sd.S;
+      const double Z = cum[j];
+      rho = Z / (Sd * ms);
+      const double dlnS = (j == NW) ? 0.0 : sd.dlnS_dm;
+      drho = dm * (1.0 / m - rho * (dlnS + s / m));
+      // d rho / d beta = Z_beta/(S m^s) - rho ln m
+      g[0] = cumg[0][j] / (Sd * ms) - rho * log(m);
+      // d rho / d m_min at fixed m1 = [Z_mmin - Z d ln S/d m_min] / (S m^s), d ln S / d m_min = -dlnS_dm
+      g[1] = (cumg[1][j] + Z * dlnS) / (Sd * ms);
+      g[2] = (cumg[2][j] - Z * ((j == NW) ? 0.0 : sd.dlnS_ddm)) / (Sd * ms);
+    }
+    T2 e;
+    e.x = (T)rho;
+    e.y = (T)(drho / NW);
+    win_tab[(size_t)b * (NW + 1) + j] = e;
+    for (int q = 0; q < 3; ++q) gfine[q][j] = g[q];
+  }
+  __syncthreads();
+  // Hermite data of the derivative tables on every second node; tangents from
+  // 5-point differences of the full grid (one-sided at the ends).
+  if (win_grad_tab) {
+    const double hf = 1.0 / NW;
+    for (int i = tid; i < 3 * (NWG + 1); i += blockDim.x) {
+      const int q = i / (NWG + 1), jc = i % (NWG + 1), j = 2 * jc;
+      const double* f = gfine[q];
+      double d;
+      if (j == 0) d = (-25 * f[0] + 48 * f[1] - 36 * f[2] + 16 * f[3] - 3 * f[4]) / (12 * hf);
+      else if (j == NW) d = (25 * f[NW] - 48 * f[NW - 1] + 36 * f[NW - 2] - 16 * f[NW - 3] + 3 * f[NW - 4]) / (12 * hf);
+      else d = (f[j - 2] - 8 * f[j - 1] + 8 * f[j + 1] - f[j + 2]) / (12 * hf);
+      T2 e;
+      e.x = (T)f[j];
+      e.y = (T)(d / NWG);
+      win_grad_tab[((size_t)b * 3 + q) * (NWG + 1) + jc] = e;
+    }
+  }
+
+  if (tid == 0) {
+    LamC<T> c;
+    const double r2pi = 2.5066282746310002;
+    double lnbP, dbPa, dbPmin, dbPmax;
+    if (fabs(alpha - 1.0) < 1e-10) {
+      const double lr = log(mmax / mmin);
+      lnbP = -log(lr);
+      dbPa = 0.5 * (log(mmax) + log(mmin));     // limit of the alpha derivative at alpha = 1
+      dbPmin = 1.0 / (mmin * lr);
+      dbPmax = -1.0 / (mmax * lr);
+    } else {
+      const double a1 = 1.0 - alpha;
+      const double A = exp(a1 * log(mmax)), Bm = exp(a1 * log(mmin));
+      lnbP = log(fabs(a1)) - log(fabs(A - Bm));
+      // d/d alpha of ln|1-alpha| - ln|A - B|, with dA/dalpha = -A ln mmax
+      dbPa = -1.0 / a1 + (A * log(mmax) - Bm * log(mmin)) / (A - Bm);
+      dbPmin = a1 * Bm / mmin / (A - Bm);
+      dbPmax = -a1 * A / mmax / (A - Bm);
+    }
+    const double lnbL = -log(sL * r2pi) - (ok ? log_dPhi(muL, sL, mmin, mmax) : 0.0);
+    const double lnbH = -log(sH * r2pi) - (ok ? log_dPhi(muH, sH, mmin, mmax) : 0.0);
+    // derivatives of -ln dPhi with respect to mu, sigma, mmin, mmax
+    auto dnorm = [&](double mu, double sg, double& dmu, double& dsg, double& dlo, double& dhi) {
+      const double a = (mmin - mu) / sg, bb = (mmax - mu) / sg;
+      const double dP = exp(ok ? log_dPhi(mu, sg, mmin, mmax) : 0.0);
+      const double pa = exp(-0.5 * a * a) / r2pi, pb = exp(-0.5 * bb * bb) / r2pi;
+      dmu = -(-pb + pa) / sg / dP;
+      dsg = -1.0 / sg - (-pb * bb + pa * a) / sg / dP;
+      dlo = pa / sg / dP;
+      dhi = -pb / sg / dP;
+    };
+    double dLmu, dLsg, dLlo, dLhi, dHmu, dHsg, dHlo, dHhi;
+    dnorm(muL, sL, dLmu, dLsg, dLlo, dLhi);
+    dnorm(muH, sH, dHmu, dHsg, dHlo, dHhi);
+    const double l2 = LOG2E;
+    c.H0 = (T)H0;
+    c.u_max = (T)umax;
+    c.inv_hv = (T)(1.0 / hv);
+    c.Om = (T)Om;
+    c.OL = (T)(1.0 - Om);
+    c.c0 = (T)log2(H0 / C_KMS);
+    c.alpha = (T)alpha;
+    c.beta = (T)beta;
+    c.mmin = (T)mmin;
+    c.mmax = (T)mmax;
+    c.dm = (T)dm;
+    c.inv_dm = dm > 0 ? (T)(1.0 / dm) : (T)0;
+    c.cP = (T)((lg < 1 ? log(1.0 - lg) : -INFINITY) * l2 + lnbP * l2);
+    c.cL = (T)((lg * ll > 0 ? log(lg * ll) : -INFINITY) * l2 + lnbL * l2);
+    c.cH = (T)((lg * (1 - ll) > 0 ? log(lg * (1 - ll)) : -INFINITY) * l2 + lnbH * l2);
+    c.muL = (T)muL;
+    c.kL = (T)(-l2 / (2 * sL * sL));
+    c.muH = (T)muH;
+    c.kH = (T)(-l2 / (2 * sH * sH));
+    c.s = (T)s;
+    c.inv_s = (T)(1.0 / s);
+    c.lM = (T)log2(M);
+    c.zw = (T)zw_s[0];
+    c.gm3 = (T)(gam - 3.0);
+    c.gk = (T)(gam + kap);
+    c.Lp = (T)log2(1.0 + zp);
+    c.dbP_alpha = (T)dbPa;
+    c.dbP_mmin = (T)dbPmin;
+    c.dbP_mmax = (T)dbPmax;
+    c.dbL_mu = (T)dLmu;
+    c.dbL_sig = (T)dLsg;
+    c.dbL_mmin = (T)dLlo;
+    c.dbL_mmax = (T)dLhi;
+    c.dbH_mu = (T)dHmu;
+    c.dbH_sig = (T)dHsg;
+    c.dbH_mmin = (T)dHlo;
+    c.dbH_mmax = (T)dHhi;
+    c.sigL = (T)sL;
+    c.sigH = (T)sH;
+    c.lg = (T)lg;
+    c.ll = (T)ll;
+    c.zw_beta = (T)zw_s[1];
+    c.zw_mmin = (T)zw_s[2];
+    c.zw_dm = (T)zw_s[3];
+    c.gamma = (T)gam;
+    c.kappa = (T)kap;
+    c.inv_opzp = (T)(1.0 / (1.0 + zp));
+    c.valid = ok ? 1 : 0;
+    c.pad_ = 0;
+    lamc[b] = c;
+    valid_out[b] = c.valid;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-sample weight (and optionally its log-derivatives)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T hermite(T t, T y0, T d0, T y1, T d1) {
+  const T t2 = t * t, t3 = t2 * t;
+  const T h01 = (T)3 * t2 - (T)2 * t3;
+  const T h11 = t3 - t2;
+  const T h10 = h11 - t2 + t;
+  return y0 + h01 * (y1 - y0) + h10 * d0 + h11 * d1;
+}
+template <typename T>
+__device__ __forceinline__ T hermite_dt(T t, T y0, T d0, T y1, T d1) {
+  const T t2 = t * t;
+  const T dh01 = (T)6 * (t - t2);
+  const T dh11 = (T)3 * t2 - (T)2 * t;
+  const T dh10 = dh11 - (T)2 * t + (T)1;
+  return dh01 * (y1 - y0) + dh10 * d0 + dh11 * d1;
+}
+
+// phi(x) = (e^x - 1)/x for |x| < 1/2 (Taylor, relative error < 1e-9) and its derivative.
+template <typename T>
+__device__ __forceinline__ T phi_series(T x) {
+  T p = (T)(1.0 / 40320);
+  p = p * x + (T)(1.0 / 5040);
+  p = p * x + (T)(1.0 / 720);
+  p = p * x + (T)(1.0 / 120);
+  p = p * x + (T)(1.0 / 24);
+  p = p * x + (T)(1.0 / 6);
+  p = p * x + (T)0.5;
+  return p * x + (T)1;
+}
+template <typename T>
+__device__ __forceinline__ T dphi_series(T x) {   // sum (j+1) x^j / (j+2)!
+  T p = (T)(8.0 / 362880);
+  p = p * x + (T)(7.0 / 40320);
+  p = p * x + (T)(6.0 / 5040);
+  p = p * x + (T)(5.0 / 720);
+  p = p * x + (T)(4.0 / 120);
+  p = p * x + (T)(3.0 / 24);
+  p = p * x + (T)(2.0 / 6);
+  return p * x + (T)0.5;
+}
+
+template <typename T>
+struct TabView {
+  const typename V2<T>::t* cos;   // [(NU+1)][GL]
+  const typename V2<T>::t* win;   // [(NW+1)][GL]
+  const typename V2<T>::t* wg;     // [3][(NWG+1)][GL]
+};
+
+// Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
+// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).
+template <typename T, int GL, bool GRAD>
+__device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
+                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
+                                            T& lin_out, T* g) {
+  using M = Mth<T>;
+  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
+  const T ln2 = (T)LN2;
+  // Eq. (1) inverted: u = d_L H0 / c = (1+z) I(z); z = u * y(v), v = sqrt(1+4u).
+  const T u = sp.dlc * c.H0;
+  bool ok = u <= c.u_max;
+  const T v = M::sqrt((T)1 + (T)4 * u);
+  const T xv = (v - (T)1) * c.inv_hv;
+  int k = (int)xv;
+  k = k < 0 ? 0 : (k > NU - 1 ? NU - 1 : k);
+  const T tv_ = xv - (T)k;
+  const auto A = tv.cos[k * GL + lam];
+  const auto Bn = tv.cos[(k + 1) * GL + lam];
+  const T y = hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
+  const T z = u * y;
+  const T opz = (T)1 + z;
+  const T L = M::log2(opz);
+  const T r = M::rcp(opz);
+  const T m1 = sp.m1d * r, m2 = sp.m2d * r;
+  const T lm1 = sp.lm1d - L, lm2 = sp.lm2d - L;
+  (void)lm2;
+  ok = ok && (m1 <= c.mmax) && (m2 > c.mmin) && (m2 <= m1);
+  // p_LOS(z): linear interpolation of the pixel's table (Eq. 5).
+  const T xz = z * inv_dz;
+  int kz = (int)xz;
+  kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
+  const T fz = xz - (T)kz;
+  const T l0 = (T)los[kz], l1 = (T)los[kz + 1];
+  const T losv = l0 + fz * (l1 - l0);
+  ok = ok && (losv > (T)0);
+  // Jacobian: |J| = (1+z)^2 (c/H0) D'(z), D' = I + (1+z)/E, I = u/(1+z).
+  const T E2 = c.Om * opz * opz * opz + c.OL;
+  const T rE = M::rsqrt(E2);
+  const T Dp = u * r + opz * rE;
+  // Madau-Dickinson: psi/(1+z) = (1+z)^(gamma-1) / (1 + 2^eX).
+  const T eX = c.gk * (L - c.Lp);
+  const T aX = M::exp2(-fabs(eX));
+  const T Xf = (T)1 + aX;
+  // Mixture (in log2): power law, low peak, high peak.
+  const T tP = c.cP - c.alpha * lm1;
+  const T dLo = m1 - c.muL, dHi = m1 - c.muH;
+  const T tL = c.cL + c.kL * dLo * dLo;
+  const T tH = c.cH + c.kH * dHi * dHi;
+  const T mx = fmax(tP, fmax(tL, tH));
+  // Conditional-mass normaliser over m1^(beta+1): rho (window table or closed form).
+  const T t1 = (m1 - c.mmin) * c.inv_dm;
+  const bool inwin = t1 < (T)1;
+  const T xw = t1 * (T)NW;
+  int kw = (int)xw;
+  kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);
+  const T tw = xw - (T)kw;
+  const auto Wa = tv.win[kw * GL + lam];
+  const auto Wb = tv.win[(kw + 1) * GL + lam];
+  const T rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
+  const T ell2 = fmax(lm1 - c.lM, (T)0);       // log2(m1 / M) above the window
+  const T sl = c.s * ell2;
+  const T Em = M::exp2(-sl);                  // (M/m1)^s
+  const T xs = -sl * ln2;
+  const bool small = fabs(xs) < (T)0.5;
+  const T ellphi = small ? ell2 * ln2 * phi_series<T>(xs) : ((T)1 - Em) * c.inv_s;
+  const T rho_a = c.zw * Em + ellphi;
+  const T rho = inwin ? rho_w : rho_a;
+  ok = ok && (rho > (T)0);
+  // Smoothing of m2: S = 1/(1 + 2^Y) in window.
+  const T mp2 = m2 - c.mmin;
+  const bool w2 = mp2 < c.dm;
+  const T mq = mp2 * (mp2 - c.dm);
+  const T rq = M::rcp(mq);
+  const T Y = w2 ? c.dm * ((T)2 * mp2 - c.dm) * rq * (T)LOG2E : (T)(-1e30);
+  const T aS = M::exp2(-fabs(Y));
+  const T Sf = (T)1 + aS;
+  // Total: w = 2^E * los * mix / (Dp * Xf * rho * Sf).
+  const T E = c.c0 + c.gm3 * L - fmax(eX, (T)0) + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp;
+  const T En = M::fl(E);
+  const T f = E - En;
+  const T eP = M::exp2(tP - mx + f), eL = M::exp2(tL - mx + f), eH = M::exp2(tH - mx + f);
+  const T mixf = eP + eL + eH;
+  const T den = Dp * Xf * rho * Sf;
+  const T rden = M::rcp(den);
+  T lin = losv * mixf * rden;
+  ok = ok && (lin == lin) && (lin < (T)3.0e38);
+  n_out = ok ? (int)En : R_SENTINEL;
+  lin_out = ok ? lin : (T)0;
+
+  if constexpr (GRAD) {
+    if (!ok) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) g[p] = (T)0;
+      return;
+    }
+    const T rmix = M::rcp(mixf);
+    const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;
+    const T rDp = rden * Xf * rho * Sf;      // 1/Dp
+    const T rXf = rden * Dp * rho * Sf;      // 1/Xf
+    const T rrho = rden * Dp * Xf * Sf;      // 1/rho
+    const T rSf = rden * Dp * Xf * rho;      // 1/Sf
+    const T lnm1 = lm1 * ln2;
+    const T lnq = sp.lq * ln2;
+    // rate pieces: sigma = X/(1+X)
+    const T sig = (eX > (T)0 ? (T)1 : aX) * rXf;
+    const T lratio = (L - c.Lp) * ln2;        // ln((1+z)/(1+z_p))
+    // d ln Mix / d m1
+    const T dmix_dm1 = -c.alpha * fP * M::rcp(m1) + (T)2 * c.kL * (T)LN2 * dLo * fL + (T)2 * c.kH * (T)LN2 * dHi * fH;
+    // m1 d ln rho / d m1
+    T m1dlnrho;
+    if (inwin) {
+      m1dlnrho = m1 * hermite_dt<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y) * (T)NW * c.inv_dm * rrho;
+    } else {
+      m1dlnrho = Em * ((T)1 - c.s * c.zw) * rrho;
+    }
+    // S(m2) derivatives: d ln S/dm2 = (1-S)(dm/m'^2 + dm/(m'-dm)^2)
+    T dlnS2_dm = 0, dlnS2_ddm = 0;
+    if (w2) {
+      const T omS = (Y > (T)0 ? (T)1 : aS) * rSf;
+      const T inv_mp = (mp2 - c.dm) * rq, inv_mq = mp2 * rq;   // 1/m', 1/(m'-dm)
+      dlnS2_dm = omS * c.dm * (inv_mp * inv_mp + inv_mq * inv_mq);
+      dlnS2_ddm = -omS * (inv_mp + mp2 * inv_mq * inv_mq);
+    }
+    // d ln w / dz at fixed Lambda (LOS slope, rate, Jacobian, mass chain)
+    const T dlos = (l1 - l0) * inv_dz;
+    const T Dpp = rE * ((T)2 - (T)1.5 * c.Om * opz * opz * opz * rE * rE);
+    T Gz = dlos * M::rcp(losv) + ((c.gm3 + (T)2) - sig * c.gk) * r - (T)2 * r - Dpp * rDp;
+    Gz -= r * (m1 * dmix_dm1 - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
+    // d z / d H0 and d z / d Omega_m
+    const T dz_dH0 = u * rDp * M::rcp(c.H0);
+    const T I = u * r;
+    T dI_dOm;
+    const T Om = c.Om;
+    if (Om < (T)1e-6) {
+      dI_dOm = (T)(-0.5) * ((opz * opz * opz * opz - (T)1) * (T)0.25 - z);
+    } else if (Om > (T)(1 - 1e-6)) {
+      const T K = ((T)1 - M::exp2((T)(-3.5) * L)) / (T)3.5;
+      dI_dOm = -(I - K) * (T)0.5;
+    } else {
+      const T K = (T)(2.0 / 3.0) * (opz * rE - (T)1 + (T)0.5 * I) * M::rcp((T)1 - Om);
+      dI_dOm = -(I - K) * (T)0.5 * M::rcp(Om);
+    }
+    const T dDp_dOm = dI_dOm - (T)0.5 * opz * (opz * opz * opz - (T)1) * rE * rE * rE;
+    const T dz_dOm = -opz * dI_dOm * rDp;
+    g[0] = M::rcp(c.H0) + Gz * dz_dH0;
+    g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
+    g[2] = fP * (c.dbP_alpha - lnm1);
+    // beta: ln q - (d rho / d beta) / rho
+    T drho_b, drho_mmin, drho_dm;
+    if (inwin) {
+      constexpr int NWG = Tab<T>::NWG;
+      const T xg = t1 * (T)NWG;
+      int kg = (int)xg;
+      kg = kg < 0 ? 0 : (kg > NWG - 1 ? NWG - 1 : kg);
+      const T tg = xg - (T)kg;
+      const auto* wg = tv.wg;
+      const auto Ga = wg[(0 * (NWG + 1) + kg) * GL + lam], Gb = wg[(0 * (NWG + 1) + kg + 1) * GL + lam];
+      const auto Ha = wg[(1 * (NWG + 1) + kg) * GL + lam], Hb = wg[(1 * (NWG + 1) + kg + 1) * GL + lam];
+      const auto Ka = wg[(2 * (NWG + 1) + kg) * GL + lam], Kb = wg[(2 * (NWG + 1) + kg + 1) * GL + lam];
+      drho_b = hermite<T>(tg, Ga.x, Ga.y, Gb.x, Gb.y);
+      drho_mmin = hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
+      drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
+    } else {
+      const T ell = ell2 * ln2;
+      const T dph = small ? dphi_series<T>(xs) : (xs * M::exp2(xs * (T)LOG2E) - M::exp2(xs * (T)LOG2E) + (T)1) * M::rcp(xs * xs);
+      drho_b = c.zw_beta * Em - ell * ell * dph - lnm1 * c.zw * Em;
+      drho_mmin = c.zw_mmin * Em;
+      drho_dm = c.zw_dm * Em;
+    }
+    g[3] = lnq - drho_b * rrho;
+    g[4] = fP * c.dbP_mmin + fL * c.dbL_mmin + fH * c.dbH_mmin - dlnS2_dm - drho_mmin * rrho;
+    g[5] = fP * c.dbP_mmax + fL * c.dbL_mmax + fH * c.dbH_mmax;
+    g[6] = dlnS2_ddm - drho_dm * rrho;
+    const T isL = M::rcp(c.sigL), isH = M::rcp(c.sigH);
+    g[7] = fL * (c.dbL_mu + dLo * isL * isL);
+    g[8] = fL * (c.dbL_sig + dLo * dLo * isL * isL * isL);
+    g[9] = fH * (c.dbH_mu + dHi * isH * isH);
+    g[10] = fH * (c.dbH_sig + dHi * dHi * isH * isH * isH);
+    const T aPg = c.lg < (T)1 ? M::rcp((T)1 - c.lg) : (T)0;
+    const T aLg = c.lg > (T)0 ? M::rcp(c.lg) : (T)0;
+    const T aLl = c.ll > (T)0 ? M::rcp(c.ll) : (T)0;
+    const T aHl = c.ll < (T)1 ? M::rcp((T)1 - c.ll) : (T)0;
+    g[11] = -fP * aPg + (fL + fH) * aLg;
+    g[12] = fL * aLl - fH * aHl;
+    g[13] = L * ln2 - sig * lratio;
+    g[14] = -sig * lratio;
+    g[15] = sig * c.gk * c.inv_opzp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exponent-tracked FP64 accumulation
+// ---------------------------------------------------------------------------
+template <bool GRAD>
+struct Acc {
+  int R;
+  double S1, S2;
+  double G[GRAD ? 16 : 1];
+  __device__ __forceinline__ void zero() {
+    R = R_SENTINEL;
+    S1 = 0;
+    S2 = 0;
+#pragma unroll
+    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+  }
+  __device__ __forceinline__ void rescale(int Rn) {   // Rn >= R
+    const int d = R - Rn;
+    S1 = ldexp(S1, d);
+    S2 = ldexp(S2, 2 * d);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], d);
+    }
+    R = Rn;
+  }
+  // add another accumulator (values scaled by 2^o.R)
+  __device__ __forceinline__ void merge(const Acc& o) {
+    const int Rm = R > o.R ? R : o.R;
+    const int da = R - Rm, db = o.R - Rm;
+    S1 = ldexp(S1, da) + ldexp(o.S1, db);
+    S2 = ldexp(S2, 2 * da) + ldexp(o.S2, 2 * db);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], da) + ldexp(o.G[p], db);
+    }
+    R = Rm;
+  }
+  template <typename T>
+  __device__ __forceinline__ void add(int n, T lin, const T* g) {
+    if (lin > (T)0) {
+      if (n > R + RESCALE_MARGIN) rescale(n);
+      const double W = ldexp((double)lin, n - R);
+      S1 += W;
+      S2 = fma(W, W, S2);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) G[p] = fma(W, (double)g[p], G[p]);
+      }
+    }
+  }
+  __device__ __forceinline__ void xor_merge(int off) {
+    Acc o;
+    o.R = __shfl_xor(R, off);
+    o.S1 = __shfl_xor(S1, off);
+    o.S2 = __shfl_xor(S2, off);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) o.G[p] = __shfl_xor(G[p], off);
+    }
+    merge(o);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// sweep
+// ---------------------------------------------------------------------------
+template <typename T, int GL, bool GRAD>
+__global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
+  using T2 = typename V2<T>::t;
+  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
+  constexpr int NS = 64 / GL;
+  constexpr int NF = GRAD ? NF_GRAD : NF_FWD;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2* cosL = reinterpret_cast<T2*>(smem);
+  T2* winL = cosL + (NU + 1) * GL;
+  T2* wgL = winL + (NW + 1) * GL;
+  const int tile = blockIdx.y;
+  const int tid = threadIdx.x;
+  const T2* cos_g = reinterpret_cast<const T2*>(a.cos_tab);
+  const T2* win_g = reinterpret_cast<const T2*>(a.win_tab);
+  const T2* wg_g = reinterpret_cast<const T2*>(a.win_grad_tab);
+  for (int i = tid; i < (NU + 1) * GL; i += blockDim.x) {
+    const int k = i / GL, l = i % GL, b = tile * GL + l;
+    cosL[i] = b < a.B ? cos_g[(size_t)b * (NU + 1) + k] : T2{};
+  }
+  for (int i = tid; i < (NW + 1) * GL; i += blockDim.x) {
+    const int k = i / GL, l = i % GL, b = tile * GL + l;
+    winL[i] = b < a.B ? win_g[(size_t)b * (NW + 1) + k] : T2{};
+  }
+  if constexpr (GRAD) {
+    constexpr int NWG = Tab<T>::NWG;
+    for (int i = tid; i < 3 * (NWG + 1) * GL; i += blockDim.x) {
+      const int q = i / ((NWG + 1) * GL), rem = i % ((NWG + 1) * GL);
+      const int k = rem / GL, l = rem % GL, b = tile * GL + l;
+      wgL[i] = b < a.B ? wg_g[((size_t)b * 3 + q) * (NWG + 1) + k] : T2{};
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int lam = lane % GL;
+  const int sg = lane / GL;
+  const int b = tile * GL + lam;
+  const bool active = b < a.B;
+  const LamC<T>* lamc = reinterpret_cast<const LamC<T>*>(a.lamc);
+  const LamC<T> c = lamc[active ? b : 0];
+  const bool live = active && c.valid;
+  const TabView<T> tv{cosL, winL, wgL};
+  const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
+  const Samp<T>* __restrict__ inj = reinterpret_cast<const Samp<T>*>(a.inj);
+  const T inv_dz = (T)((a.n_z - 1) / a.z_max);
+  T g[GRAD ? 16 : 1];
+
+  for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
+    const WorkItem w = a.items[a.order[it]];
+    Acc<GRAD> chunk;
+    chunk.zero();
+    int npass = 0;
+    if (w.event >= 0) {
+      for (int p = w.pix0; p < w.pix1; ++p) {
+        const int64_t s0 = a.pix_off[p], s1 = a.pix_off[p + 1];
+        const float* __restrict__ tab = a.los + (size_t)a.pix_row[p] * a.n_z;
+        Acc<GRAD> pix;
+        pix.zero();
+        for (int64_t sb = s0; sb < s1; sb += NS) {
+          const int64_t s = sb + sg;
+          if (s < s1 && live) {
+            const Samp<T> sp = samp[s];
+            int n;
+            T lin;
+            eval_weight<T, GL, GRAD>(sp, c, tv, lam, tab, a.n_z, inv_dz, n, lin, g);
+            pix.template add<T>(n, lin, g);
+          }
+        }
+#pragma unroll
+        for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
+        bool pass;
+        if (a.gate_mode == 2) pass = pix.S1 > 0;
+        else pass = pix.S2 > 0 && pix.S1 * pix.S1 >= a.neff_min * pix.S2;
+        if (pass) {
+          chunk.merge(pix);
+          ++npass;
+        }
+      }
+    } else {
+      for (int64_t sb = w.s0; sb < w.s1; sb += NS) {
+        const int64_t s = sb + sg;
+        if (s < w.s1 && live) {
+          const Samp<T> sp = inj[s];
+          int n;
+          T lin;
+          eval_weight<T, GL, GRAD>(sp, c, tv, lam, a.sky, a.n_z, inv_dz, n, lin, g);
+          chunk.template add<T>(n, lin, g);
+        }
+      }
+#pragma unroll
+      for (int off = GL; off < 64; off <<= 1) chunk.xor_merge(off);
+    }
+    if (sg == 0 && active) {
+      double* out = a.part + (size_t)w.slot * NF * a.B + b;
+      out[0] = (double)chunk.R;
+      out[(size_t)a.B] = chunk.S1;
+      out[(size_t)2 * a.B] = chunk.S2;
+      out[(size_t)3 * a.B] = (double)npass;
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) out[(size_t)(4 + p) * a.B] = chunk.G[p];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// combine: per point, fixed-order reductions
+// ---------------------------------------------------------------------------
+struct Part3 {
+  double R, S1, S2;
+};
+__device__ inline Part3 pmerge(Part3 x, Part3 y) {
+  if (!(x.S1 > 0)) return y;
+  if (!(y.S1 > 0)) return x;
+  const double Rm = fmax(x.R, y.R);
+  Part3 r;
+  r.R = Rm;
+  r.S1 = ldexp(x.S1, (int)(x.R - Rm)) + ldexp(y.S1, (int)(y.R - Rm));
+  r.S2 = ldexp(x.S2, 2 * (int)(x.R - Rm)) + ldexp(y.S2, 2 * (int)(y.R - Rm));
+  return r;
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int B = a.B;
+  const double ln2 = LN2;
+  const double* P = a.part;
+  auto at = [&](int slot, int f) { return P[((size_t)slot * a.nf + f) * B + b]; };
+  const bool valid = a.valid[b] != 0;
+  __shared__ double red[256];
+  __shared__ double redg[GRAD ? 16 : 1][256];
+  __shared__ unsigned int fl[256];
+  __shared__ Part3 rp[256];
+  double acc = 0;
+  double accg[GRAD ? 16 : 1];
+#pragma unroll
+  for (int p = 0; p < (GRAD ? 16 : 1); ++p) accg[p] = 0;
+  unsigned int flags = 0;
+  for (int e = tid; e < a.n_events; e += blockDim.x) {
+    Part3 m{0, 0, 0};
+    double G[GRAD ? 16 : 1];
+#pragma unroll
+    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+    double Rg = -1e300;
+    for (int sl = a.ev_item_off[e]; sl < a.ev_item_off[e + 1]; ++sl) {
+      Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
+      if constexpr (GRAD) {
+        if (x.S1 > 0) {
+          if (x.R > Rg) {
+            for (int p = 0; p < 16; ++p) G[p] = (Rg > -1e299) ? ldexp(G[p], (int)(Rg - x.R)) : 0.0;
+            Rg = x.R;
+          }
+          for (int p = 0; p < 16; ++p) G[p] += ldexp(at(sl, 4 + p), (int)(x.R - Rg));
+        }
+      }
+      m = pmerge(m, x);
+    }
+    double lnLe, neff;
+    if (valid && m.S1 > 0) {
+      lnLe = log(m.S1) + m.R * ln2 - a.ln_ns[e];
+      neff = m.S1 * m.S1 / m.S2;
+      if (a.gate_mode == 1 && !(neff >= a.neff_min)) {
+        lnLe = -INFINITY;
+        flags |= 2u;
+      }
+    } else {
+      lnLe = -INFINITY;
+      neff = 0;
+      flags |= valid ? 2u : 0u;
+    }
+    if (a.logL_event) a.logL_event[(size_t)b * a.n_events + e] = lnLe;
+    if (a.neff_event) a.neff_event[(size_t)b * a.n_events + e] = neff;
+    acc += lnLe;
+    if constexpr (GRAD) {
+      if (m.S1 > 0) {
+        // G and S1 share the scale 2^m.R (Rg == m.R)
+        for (int p = 0; p < 16; ++p) accg[p] += G[p] / m.S1;
+      }
+    }
+  }
+  // selection term: strided partial merges, then a fixed tree
+  Part3 sel{0, 0, 0};
+  double Gs[GRAD ? 16 : 1];
+  double Rgs = -1e300;
+#pragma unroll
+  for (int p = 0; p < (GRAD ? 16 : 1); ++p) Gs[p] = 0;
+  for (int sl = a.inj_slot0 + tid; sl < a.inj_slot1; sl += blockDim.x) {
+    Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
+    if constexpr (GRAD) {
+      if (x.S1 > 0) {
+        if (x.R > Rgs) {
+          for (int p = 0; p < 16; ++p) Gs[p] = (Rgs > -1e299) ? ldexp(Gs[p], (int)(Rgs - x.R)) : 0.0;
+          Rgs = x.R;
+        }
+        for (int p = 0; p < 16; ++p) Gs[p] += ldexp(at(sl, 4 + p), (int)(x.R - Rgs));
+      }
+    }
+    sel = pmerge(sel, x);
+  }
+  red[tid] = acc;
+  fl[tid] = flags;
+  rp[tid] = sel;
+  if constexpr (GRAD) {
+    for (int p = 0; p < 16; ++p) redg[p][tid] = accg[p];
+  }
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      red[tid] += red[tid + st];
+      fl[tid] |= fl[tid + st];
+      if constexpr (GRAD) {
+        for (int p = 0; p < 16; ++p) redg[p][tid] += redg[p][tid + st];
+      }
+    }
+    __syncthreads();
+  }
+  // selection gradient needs a scale-aware tree: do it with the Part3 tree and
+  // per-thread G rescaled to the thread's own R (Rgs == rp[tid].R)
+  __shared__ double gsel[GRAD ? 16 : 1][256];
+  if constexpr (GRAD) {
+    for (int p = 0; p < 16; ++p) gsel[p][tid] = Gs[p];
+  }
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    Part3 x, y;
+    double gx[GRAD ? 16 : 1];
+    if (tid < st) {
+      x = rp[tid];
+      y = rp[tid + st];
+      if constexpr (GRAD) {
+        const bool hx = x.S1 > 0, hy = y.S1 > 0;
+        const double Rm = hx && hy ? fmax(x.R, y.R) : (hx ? x.R : y.R);
+        for (int p = 0; p < 16; ++p) {
+          const double a0 = hx ? ldexp(gsel[p][tid], (int)(x.R - Rm)) : 0.0;
+          const double a1 = hy ? ldexp(gsel[p][tid + st], (int)(y.R - Rm)) : 0.0;
+          gx[p] = a0 + a1;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < st) {
+      rp[tid] = pmerge(x, y);
+      if constexpr (GRAD) {
+        for (int p = 0; p < 16; ++p) gsel[p][tid] = gx[p];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const Part3 s = rp[0];
+    unsigned int f = fl[0];
+    double logL = -INFINITY;
+    double lna = -INFINITY;
+    if (!valid) f |= 1u;
+    if (valid && s.S1 > 0) lna = log(s.S1) + s.R * ln2 - a.ln_ndraw;
+    else if (valid) f |= 4u;
+    if (f == 0) {
+      logL = red[0] - (double)a.n_events * lna;
+      if (!isfinite(logL)) {
+        f |= 8u;
+        logL = -INFINITY;
+      }
+    }
+    a.logL[b] = logL;
+    if (a.neff_sel) a.neff_sel[b] = s.S1 > 0 ? s.S1 * s.S1 / s.S2 : 0.0;
+    if (a.flags) a.flags[b] = f;
+    if constexpr (GRAD) {
+      if (a.grad) {
+        for (int p = 0; p < 16; ++p) {
+          const double gv = (f == 0) ? redg[p][0] - (double)a.n_events * gsel[p][0] / s.S1 : 0.0;
+          a.grad[(size_t)b * 16 + p] = gv;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sample packing (once per catalogue)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void pack_kernel(const double* __restrict__ m1d, const double* __restrict__ m2d,
+                            const double* __restrict__ dl, const double* __restrict__ lnp, int64_t n,
+                            Samp<T>* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Samp<T> s;
+  const double a = m1d[i], bq = m2d[i];
+  s.m1d = (T)a;
+  s.m2d = (T)bq;
+  s.lm1d = (T)log2(a);
+  s.lm2d = (T)log2(bq);
+  s.dlc = (T)(dl[i] / C_KMS);
+  s.nlp = (T)(-lnp[i] * LOG2E);
+  s.lq = (T)log2(bq / a);
+  s.pad = (T)0;
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+size_t sweep_lds_bytes(int precision_fp32, int GL, bool grad) {
+  const size_t t1 = precision_fp32 ? sizeof(float) : sizeof(double);
+  const int NU = precision_fp32 ? NU_F32 : NU_F64, NW = precision_fp32 ? NW_F32 : NW_F64;
+  const int NWG = precision_fp32 ? NWG_F32 : NWG_F64;
+  return t1 * GL * (2 * (NU + 1) + 2 * (NW + 1) + (grad ? 6 * (NWG + 1) : 0));
+}
+
+hipError_t launch_pack(int fp32, const double* m1, const double* m2, const double* dl, const double* lnp,
+                       int64_t n, void* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int bs = 256;
+  const unsigned gs = (unsigned)((n + bs - 1) / bs);
+  if (fp32) pack_kernel<float><<<gs, bs, 0, st>>>(m1, m2, dl, lnp, n, (Samp<float>*)out);
+  else pack_kernel<double><<<gs, bs, 0, st>>>(m1, m2, dl, lnp, n, (Samp<double>*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
+                        void* win_tab, void* win_grad_tab, int* valid, hipStream_t st) {
+  if (fp32)
+    setup_kernel<float><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
+                                            (float2*)win_tab, (float2*)win_grad_tab, valid);
+  else
+    setup_kernel<double><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
+                                             (double2*)win_tab, (double2*)win_grad_tab, valid);
+  return hipGetLastError();
+}
+
+template <typename T, int GL, bool GRAD>
+static hipError_t sweep_t(const SweepArgs& a, int grid_x, int n_tiles, int threads, size_t lds, hipStream_t st) {
+  sweep_kernel<T, GL, GRAD><<<dim3(grid_x, n_tiles), threads, lds, st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int GL, bool GRAD>
+static hipError_t set_attr(int fp32) {
+  return hipFuncSetAttribute((const void*)sweep_kernel<T, GL, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sweep_lds_bytes(fp32, GL, GRAD));
+}
+
+// Raise the dynamic-LDS limit of every sweep variant (once, outside any capture).
+hipError_t init_kernel_attrs() {
+  hipError_t e = hipSuccess;
+#define DSL_ATTR(T, G, F)                         \
+  if (e == hipSuccess) e = set_attr<T, G, true>(F); \
+  if (e == hipSuccess) e = set_attr<T, G, false>(F);
+  DSL_ATTR(float, 1, 1)
+  DSL_ATTR(float, 4, 1)
+  DSL_ATTR(float, 16, 1)
+  DSL_ATTR(float, 64, 1)
+  DSL_ATTR(double, 1, 0)
+  DSL_ATTR(double, 4, 0)
+#undef DSL_ATTR
+  return e;
+}
+
+hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st) {
+  const int n_tiles = (a.B + GL - 1) / GL;
+  const size_t lds = sweep_lds_bytes(fp32, GL, grad);
+#define DSL_CASE(T, G)                                                         \
+  if (GL == G) return grad ? sweep_t<T, G, true>(a, grid_x, n_tiles, threads, lds, st) \
+                           : sweep_t<T, G, false>(a, grid_x, n_tiles, threads, lds, st);
+  if (fp32) {
+    DSL_CASE(float, 1)
+    DSL_CASE(float, 4)
+    DSL_CASE(float, 16)
+    DSL_CASE(float, 64)
+  } else {
+    DSL_CASE(double, 1)
+    DSL_CASE(double, 4)
+  }
+#undef DSL_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
+  if (grad) combine_kernel<true><<<a.B, 256, 0, st>>>(a);
+  else combine_kernel<false><<<a.B, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace dsl

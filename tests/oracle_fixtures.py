@@ -78,6 +78,8 @@ def toy_injection_nodes(H0, mu, sigma, mmin, z_max, n_d=60, n_gh=40, n_gl=2):
             m1d = mu_d + sg_d * tk
             W1 = wk * math.exp(0.5 * tk * tk) * sg_d
             a, b = mmin * (1.0 + z), m1d
+            if b <= a:          # p1 vanishes below m_min: no contribution
+                continue
             for xl, wl in zip(xg, wg):
                 m1.append(m1d)
                 m2.append(0.5 * (b - a) * (xl + 1.0) + a)

@@ -1,0 +1,160 @@
+"""Edge cases, determinism and graph replay of the HIP path (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import TOL_LOGL_FP32, check_events, log, need_gpu, rel_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    need_gpu()
+    import torch
+    from oracle import dsl_oracle as O
+    from paper_2605_23538_amd import binding, synth
+    return dict(torch=torch, O=O, binding=binding, synth=synth)
+
+
+def ragged_catalog(synth, sizes, n_inj=777, seed=0):
+    """One event per entry of `sizes`, each a list of pixel sample counts."""
+    rng = np.random.default_rng(seed)
+    epo, pso = [0], [0]
+    for ev in sizes:
+        for n in ev:
+            pso.append(pso[-1] + n)
+        epo.append(epo[-1] + len(ev))
+    n = pso[-1]
+    m1 = rng.uniform(10, 80, n)
+    q = rng.uniform(0.3, 1, n)
+    dl = rng.lognormal(math.log(1500), 0.3, n)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    n_pix = len(pso) - 1
+    zg = np.linspace(0, 2, 256)
+    los = np.stack([1 + 0.8 * np.sin(7 * zg + k) ** 2 for k in range(n_pix)]).astype(np.float32)
+    im1 = rng.uniform(8, 90, n_inj)
+    iq = rng.uniform(0.2, 1, n_inj)
+    idl = rng.uniform(100, 6000, n_inj)
+    return synth.Catalog(
+        event_pix_off=np.asarray(epo, np.int64), pix_samp_off=np.asarray(pso, np.int64),
+        pix_los_row=np.arange(n_pix, dtype=np.int32), los=los, sky_z=np.ones(256, np.float32), z_max=2.0,
+        m1d=f32(m1), m2d=f32(m1 * q), dl=f32(dl), ln_pi=f32(2 * np.log(dl)),
+        inj_m1d=f32(im1), inj_m2d=f32(im1 * iq), inj_dl=f32(idl),
+        inj_ln_pdraw=f32(-2 * np.log(im1) + 2 * np.log(idl) - 21.0), n_draw=5000)
+
+
+RAGGED = [[1, 2, 63, 64, 65], [0, 130, 0, 7], [1], [200], [3, 3, 3, 3, 3, 3, 3]]
+
+
+@pytest.mark.parametrize("precision,tile", [("fp32", 1), ("fp32", 4), ("fp32", 16), ("fp32", 64),
+                                            ("fp64", 1), ("fp64", 4)])
+@pytest.mark.parametrize("chunk", [64, 0])
+def test_ragged_pixels_and_items(mods, precision, tile, chunk):
+    """Pixels of 0, 1, 2, 63, 64, 65, 130, 200 samples; items split mid-event."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = ragged_catalog(synth, RAGGED)
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision=precision)
+    lik.set_option("lambda_tile", tile)
+    lik.set_option("chunk", chunk)
+    lam = synth.draw_lambdas(5, seed=21)
+    lam[0] = synth.fiducial_lambda()
+    r = lik.loglike(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    tol = TOL_LOGL_FP32 if precision == "fp32" else 1e-10
+    for b in range(len(lam)):
+        ref = O.loglike(cat, lam[b], margins=True)
+        assert int(r["flags"][b]) == ref["flags"], (b, int(r["flags"][b]), ref["flags"])
+        ev = r["logL_event"][b].cpu().numpy()
+        check_events(ev, r["neff_event"][b].cpu().numpy(), ref, tol)
+        if not ref["flags"]:
+            assert rel_close(float(r["logL"][b]), ref["logL"], tol)
+    lik.close()
+
+
+def test_flags_invalid_lambda_and_failing_gate(mods):
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = ragged_catalog(synth, RAGGED)
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision="fp32")
+    lam = np.stack([synth.fiducial_lambda()] * 6)
+    lam[1, 4] = 100.0          # m_min > m_max
+    lam[2, 1] = 1.5            # Omega_m > 1
+    lam[3, 8] = -1.0           # sigma_low < 0
+    lam[4, 11] = 1.2           # lambda_g > 1
+    lam[5, 0] = float("nan")
+    r = lik.loglike(torch.tensor(lam, device="cuda"))
+    fl = r["flags"].cpu().numpy()
+    lg = r["logL"].cpu().numpy()
+    # the one-sample event cannot pass the N_eff >= 2 gate: flag 2, as in the oracle
+    ref = O.loglike(cat, lam[0])
+    assert fl[0] == ref["flags"] == 2 and lg[0] == -math.inf
+    for b in range(1, 6):
+        assert fl[b] & 1 and lg[b] == -math.inf
+    # a gate nothing passes: every event flagged, ln L = -inf
+    lik.set_option("neff_min", 1e9)
+    r = lik.loglike(torch.tensor(lam[:1], device="cuda"), per_event=True)
+    assert int(r["flags"][0]) & 2 and float(r["logL"][0]) == -math.inf
+    assert np.all(np.isneginf(r["logL_event"][0].cpu().numpy()))
+    # gate modes 0, 1 (event gate) and 2 (no gate) against the oracle
+    for mode in (0, 1, 2):
+        lik.set_option("neff_min", 2.0)
+        lik.set_option("gate_mode", mode)
+        r = lik.loglike(torch.tensor(lam[:1], device="cuda"), per_event=True)
+        ref = O.loglike(cat, lam[0], gate_mode=mode, margins=True)
+        assert int(r["flags"][0]) == ref["flags"]
+        check_events(r["logL_event"][0].cpu().numpy(), r["neff_event"][0].cpu().numpy(), ref, TOL_LOGL_FP32)
+    lik.close()
+
+
+def test_bad_arguments_raise(mods):
+    torch, synth, binding = mods["torch"], mods["synth"], mods["binding"]
+    cat = ragged_catalog(synth, RAGGED)
+    lik = binding.DarkSirenLikelihood(cat)
+    lik.set_option("max_batch", 4)
+    with pytest.raises(binding.DSLError):
+        lik.loglike(torch.zeros(5, 16, dtype=torch.float64, device="cuda"))
+    with pytest.raises(binding.DSLError):
+        lik.set_option("lambda_tile", 3)
+    with pytest.raises(binding.DSLError):
+        lik.set_option("nonsense", 1)
+    lik.close()
+
+
+def test_determinism_and_graph_replay(mods):
+    """Repeated calls are bitwise equal; graph replays (with eager work and
+    synchronisations in between) equal the eager launch sequence."""
+    torch, synth = mods["torch"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    lam = torch.tensor(synth.draw_lambdas(70, seed=9), device="cuda")
+    lik.set_option("graph", 0)
+    eager = lik.loglike_grad(lam)
+    e_l, e_g = eager["logL"].clone(), eager["grad"].clone()
+    lik.set_option("graph", 1)
+    outs = []
+    logL = torch.empty(70, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        r = lik.loglike_grad(lam)
+        _ = (lam * 2).sum()            # unrelated eager work between replays
+        torch.cuda.synchronize()
+        outs.append((r["logL"].clone(), r["grad"].clone()))
+    for l, g in outs:
+        assert torch.equal(torch.nan_to_num(l, neginf=-1e300), torch.nan_to_num(e_l, neginf=-1e300))
+        assert torch.equal(g, e_g)
+    log("  4 graph replays bitwise equal to eager")
+    lik.close()
+
+
+def test_autograd_function(mods):
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=3, n_inj=3000)
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    lam = torch.tensor(synth.fiducial_lambda()[None].repeat(2, 0), device="cuda", requires_grad=True)
+    out = lik(lam)
+    (out * torch.tensor([1.0, 2.0], device="cuda", dtype=torch.float64)).sum().backward()
+    ref = O.loglike(cat, synth.fiducial_lambda(), grad=True)
+    g = lam.grad.cpu().numpy()
+    np.testing.assert_allclose(g[0], ref["grad"], rtol=1e-4, atol=1e-6 * np.linalg.norm(ref["grad"]))
+    np.testing.assert_allclose(g[1], 2 * ref["grad"], rtol=1e-4, atol=2e-6 * np.linalg.norm(ref["grad"]))
+    lik.close()
