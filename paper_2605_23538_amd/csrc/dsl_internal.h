@@ -47,8 +47,13 @@ struct LamC {
   T lg, ll;                                   // lambda_g, lambda_low
   T zw_beta, zw_mmin, zw_dm;                  // window integrals of d/d(beta, m_min, dm) of m^beta S, / M^s
   T gamma, kappa, inv_opzp;                   // gamma, kappa, 1/(1+z_p)
+  T inv_H0;                                   // 1/H0
+  T k23, hOm;                                 // (2/3)/(1-Om), 1/(2 Om)
+  T isL2, isL3, isH2, isH3;                   // sigma^-2, sigma^-3 of the peaks
+  T aPg, aLg, aLl, aHl;                       // 1/(1-lg), 1/lg, 1/ll, 1/(1-ll) (0 at the edges)
+  T inv_s2;                                   // 1/(beta+1)^2
+  int om_case;                                // 0 general, 1 Om ~ 0, 2 Om ~ 1
   int valid;
-  int pad_;
 };
 
 // Number of window-derivative tables used by the adjoint (beta, m_min, delta_m).
@@ -70,7 +75,7 @@ struct Samp {
   T dlc;           // d_L / c  [Mpc s/km]
   T nlp;           // -ln(prior) / ln 2
   T lq;            // log2(m2d / m1d)
-  T pad;
+  T inv_m1d;       // 1 / m1d
 };
 
 // Fields of one partial result (per work item and Lambda).

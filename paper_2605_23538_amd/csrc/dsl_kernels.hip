@@ -335,8 +335,20 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     c.gamma = (T)gam;
     c.kappa = (T)kap;
     c.inv_opzp = (T)(1.0 / (1.0 + zp));
+    c.inv_H0 = (T)(1.0 / H0);
+    c.om_case = Om < 1e-6 ? 1 : (Om > 1 - 1e-6 ? 2 : 0);
+    c.k23 = c.om_case == 0 ? (T)((2.0 / 3.0) / (1.0 - Om)) : (T)0;
+    c.hOm = c.om_case == 0 ? (T)(0.5 / Om) : (T)0;
+    c.isL2 = (T)(1.0 / (sL * sL));
+    c.isL3 = (T)(1.0 / (sL * sL * sL));
+    c.isH2 = (T)(1.0 / (sH * sH));
+    c.isH3 = (T)(1.0 / (sH * sH * sH));
+    c.aPg = lg < 1 ? (T)(1.0 / (1.0 - lg)) : (T)0;
+    c.aLg = lg > 0 ? (T)(1.0 / lg) : (T)0;
+    c.aLl = ll > 0 ? (T)(1.0 / ll) : (T)0;
+    c.aHl = ll < 1 ? (T)(1.0 / (1.0 - ll)) : (T)0;
+    c.inv_s2 = (T)(1.0 / (s * s));
     c.valid = ok ? 1 : 0;
-    c.pad_ = 0;
     lamc[b] = c;
     valid_out[b] = c.valid;
   }
@@ -489,7 +501,8 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       for (int p = 0; p < 16; ++p) g[p] = (T)0;
       return;
     }
-    const T rmix = M::rcp(mixf);
+    const T Q = M::rcp(losv * mixf);          // 1/(los mix)
+    const T rmix = Q * losv, rlos = Q * mixf;
     const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;
     const T rDp = rden * Xf * rho * Sf;      // 1/Dp
     const T rXf = rden * Dp * rho * Sf;      // 1/Xf
@@ -497,11 +510,11 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     const T rSf = rden * Dp * Xf * rho;      // 1/Sf
     const T lnm1 = lm1 * ln2;
     const T lnq = sp.lq * ln2;
-    // rate pieces: sigma = X/(1+X)
+    // rate pieces: sig = X/(1+X)
     const T sig = (eX > (T)0 ? (T)1 : aX) * rXf;
     const T lratio = (L - c.Lp) * ln2;        // ln((1+z)/(1+z_p))
-    // d ln Mix / d m1
-    const T dmix_dm1 = -c.alpha * fP * M::rcp(m1) + (T)2 * c.kL * (T)LN2 * dLo * fL + (T)2 * c.kH * (T)LN2 * dHi * fH;
+    // m1 d ln Mix / d m1
+    const T m1dmix = -c.alpha * fP - m1 * (dLo * c.isL2 * fL + dHi * c.isH2 * fH);
     // m1 d ln rho / d m1
     T m1dlnrho;
     if (inwin) {
@@ -520,25 +533,24 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     // d ln w / dz at fixed Lambda (LOS slope, rate, Jacobian, mass chain)
     const T dlos = (l1 - l0) * inv_dz;
     const T Dpp = rE * ((T)2 - (T)1.5 * c.Om * opz * opz * opz * rE * rE);
-    T Gz = dlos * M::rcp(losv) + ((c.gm3 + (T)2) - sig * c.gk) * r - (T)2 * r - Dpp * rDp;
-    Gz -= r * (m1 * dmix_dm1 - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
-    // d z / d H0 and d z / d Omega_m
-    const T dz_dH0 = u * rDp * M::rcp(c.H0);
+    T Gz = dlos * rlos + (c.gm3 - sig * c.gk) * r - Dpp * rDp;
+    Gz -= r * (m1dmix - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
+    // dz/dH0 = (d_L/c)/D', dz/dOm = -(1+z) dI/dOm / D'
+    const T dz_dH0 = sp.dlc * rDp;
     const T I = u * r;
     T dI_dOm;
-    const T Om = c.Om;
-    if (Om < (T)1e-6) {
+    if (c.om_case == 0) {
+      const T K = (opz * rE - (T)1 + (T)0.5 * I) * c.k23;
+      dI_dOm = -(I - K) * c.hOm;
+    } else if (c.om_case == 1) {
       dI_dOm = (T)(-0.5) * ((opz * opz * opz * opz - (T)1) * (T)0.25 - z);
-    } else if (Om > (T)(1 - 1e-6)) {
-      const T K = ((T)1 - M::exp2((T)(-3.5) * L)) / (T)3.5;
-      dI_dOm = -(I - K) * (T)0.5;
     } else {
-      const T K = (T)(2.0 / 3.0) * (opz * rE - (T)1 + (T)0.5 * I) * M::rcp((T)1 - Om);
-      dI_dOm = -(I - K) * (T)0.5 * M::rcp(Om);
+      const T K = ((T)1 - M::exp2((T)(-3.5) * L)) * (T)(1.0 / 3.5);
+      dI_dOm = -(I - K) * (T)0.5;
     }
     const T dDp_dOm = dI_dOm - (T)0.5 * opz * (opz * opz * opz - (T)1) * rE * rE * rE;
     const T dz_dOm = -opz * dI_dOm * rDp;
-    g[0] = M::rcp(c.H0) + Gz * dz_dH0;
+    g[0] = c.inv_H0 + Gz * dz_dH0;
     g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
     g[2] = fP * (c.dbP_alpha - lnm1);
     // beta: ln q - (d rho / d beta) / rho
@@ -558,8 +570,9 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
     } else {
       const T ell = ell2 * ln2;
-      const T dph = small ? dphi_series<T>(xs) : (xs * M::exp2(xs * (T)LOG2E) - M::exp2(xs * (T)LOG2E) + (T)1) * M::rcp(xs * xs);
-      drho_b = c.zw_beta * Em - ell * ell * dph - lnm1 * c.zw * Em;
+      // ell^2 phi'(x), x = -s ell: series, or (x e^x - e^x + 1)/s^2 with e^x = Em
+      const T l2dph = small ? ell * ell * dphi_series<T>(xs) : (xs * Em - Em + (T)1) * c.inv_s2;
+      drho_b = c.zw_beta * Em - l2dph - lnm1 * c.zw * Em;
       drho_mmin = c.zw_mmin * Em;
       drho_dm = c.zw_dm * Em;
     }
@@ -567,17 +580,12 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     g[4] = fP * c.dbP_mmin + fL * c.dbL_mmin + fH * c.dbH_mmin - dlnS2_dm - drho_mmin * rrho;
     g[5] = fP * c.dbP_mmax + fL * c.dbL_mmax + fH * c.dbH_mmax;
     g[6] = dlnS2_ddm - drho_dm * rrho;
-    const T isL = M::rcp(c.sigL), isH = M::rcp(c.sigH);
-    g[7] = fL * (c.dbL_mu + dLo * isL * isL);
-    g[8] = fL * (c.dbL_sig + dLo * dLo * isL * isL * isL);
-    g[9] = fH * (c.dbH_mu + dHi * isH * isH);
-    g[10] = fH * (c.dbH_sig + dHi * dHi * isH * isH * isH);
-    const T aPg = c.lg < (T)1 ? M::rcp((T)1 - c.lg) : (T)0;
-    const T aLg = c.lg > (T)0 ? M::rcp(c.lg) : (T)0;
-    const T aLl = c.ll > (T)0 ? M::rcp(c.ll) : (T)0;
-    const T aHl = c.ll < (T)1 ? M::rcp((T)1 - c.ll) : (T)0;
-    g[11] = -fP * aPg + (fL + fH) * aLg;
-    g[12] = fL * aLl - fH * aHl;
+    g[7] = fL * (c.dbL_mu + dLo * c.isL2);
+    g[8] = fL * (c.dbL_sig + dLo * dLo * c.isL3);
+    g[9] = fH * (c.dbH_mu + dHi * c.isH2);
+    g[10] = fH * (c.dbH_sig + dHi * dHi * c.isH3);
+    g[11] = -fP * c.aPg + (fL + fH) * c.aLg;
+    g[12] = fL * c.aLl - fH * c.aHl;
     g[13] = L * ln2 - sig * lratio;
     g[14] = -sig * lratio;
     g[15] = sig * c.gk * c.inv_opzp;
@@ -624,7 +632,8 @@ struct Acc {
   template <typename T>
   __device__ __forceinline__ void add(int n, T lin, const T* g) {
     if (lin > (T)0) {
-      if (n > R + RESCALE_MARGIN) rescale(n);
+      if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
+      else if (n > R + RESCALE_MARGIN) rescale(n);
       const double W = ldexp((double)lin, n - R);
       S1 += W;
       S2 = fma(W, W, S2);
@@ -647,6 +656,45 @@ struct Acc {
   }
 };
 
+// Sample record loads: with one sample per wavefront (NS == 1) the address is
+// uniform, so it goes through the scalar cache (constant address space).
+template <typename T, int NS>
+__device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_t i) {
+  if constexpr (NS == 1) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(i & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(i >> 32));
+    const int64_t u = ((int64_t)hi << 32) | (uint32_t)lo;
+    return p[u];
+  } else {
+    return p[i];
+  }
+}
+
+// One run of samples [s0, s1) accumulated into acc; the next record is
+// loaded while the current one is evaluated.
+template <typename T, int GL, bool GRAD>
+__device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
+                                          bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
+                                          const float* __restrict__ tab, int n_z, T inv_dz, Acc<GRAD>& acc,
+                                          T* g) {
+  constexpr int NS = 64 / GL;
+  if (s1 <= s0) return;
+  Samp<T> nxt = ld_samp<T, NS>(base, s0 + sg < s1 ? s0 + sg : s1 - 1);
+  for (int64_t sb = s0; sb < s1; sb += NS) {
+    const Samp<T> cur = nxt;
+    if (sb + NS < s1) {
+      const int64_t ni = sb + NS + sg;
+      nxt = ld_samp<T, NS>(base, ni < s1 ? ni : s1 - 1);
+    }
+    if (sb + sg < s1 && live) {
+      int n;
+      T lin;
+      eval_weight<T, GL, GRAD>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g);
+      acc.template add<T>(n, lin, g);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // sweep
 // ---------------------------------------------------------------------------
@@ -654,7 +702,6 @@ template <typename T, int GL, bool GRAD>
 __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
-  constexpr int NS = 64 / GL;
   constexpr int NF = GRAD ? NF_GRAD : NF_FWD;
   extern __shared__ __align__(16) unsigned char smem[];
   T2* cosL = reinterpret_cast<T2*>(smem);
@@ -709,16 +756,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         const float* __restrict__ tab = a.los + (size_t)a.pix_row[p] * a.n_z;
         Acc<GRAD> pix;
         pix.zero();
-        for (int64_t sb = s0; sb < s1; sb += NS) {
-          const int64_t s = sb + sg;
-          if (s < s1 && live) {
-            const Samp<T> sp = samp[s];
-            int n;
-            T lin;
-            eval_weight<T, GL, GRAD>(sp, c, tv, lam, tab, a.n_z, inv_dz, n, lin, g);
-            pix.template add<T>(n, lin, g);
-          }
-        }
+        sweep_run<T, GL, GRAD>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         bool pass;
@@ -730,16 +768,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         }
       }
     } else {
-      for (int64_t sb = w.s0; sb < w.s1; sb += NS) {
-        const int64_t s = sb + sg;
-        if (s < w.s1 && live) {
-          const Samp<T> sp = inj[s];
-          int n;
-          T lin;
-          eval_weight<T, GL, GRAD>(sp, c, tv, lam, a.sky, a.n_z, inv_dz, n, lin, g);
-          chunk.template add<T>(n, lin, g);
-        }
-      }
+      sweep_run<T, GL, GRAD>(inj, w.s0, w.s1, sg, live, c, tv, lam, a.sky, a.n_z, inv_dz, chunk, g);
 #pragma unroll
       for (int off = GL; off < 64; off <<= 1) chunk.xor_merge(off);
     }
@@ -949,7 +978,7 @@ __global__ void pack_kernel(const double* __restrict__ m1d, const double* __rest
   s.dlc = (T)(dl[i] / C_KMS);
   s.nlp = (T)(-lnp[i] * LOG2E);
   s.lq = (T)log2(bq / a);
-  s.pad = (T)0;
+  s.inv_m1d = (T)(1.0 / a);
   out[i] = s;
 }
 
