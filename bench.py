@@ -29,6 +29,7 @@ FLOP_PER_WEIGHT_FWD = 175
 FLOP_PER_WEIGHT_GRAD = 360
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -37,11 +38,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--config", default="c4")
-    p.add_argument("--B", type=int, default=64)
+    p.add_argument("--config", default="c4", help="workload: c1 .. c5 (c4 is the benchmark)")
+    p.add_argument("--B", type=int, default=None, help="points per launch (default: the workload's)")
+    p.add_argument("--precision", default=None, choices=["fp32", "fp64"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-single", action="store_true", help="skip the one-Lambda-per-launch comparison")
-    p.add_argument("--autotune", action="store_true")
+    p.add_argument("--no-autotune", action="store_true", help="use the default tile shape and chunk")
     p.add_argument("--forward-only", action="store_true")
     return p.parse_args()
 
@@ -82,20 +84,26 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    grad = not args.forward_only
+    # workload defaults: (points per launch, precision, gradient)
+    defaults = {"c1": (1, "fp64", False), "c2": (1, "fp32", False), "c3": (512, "fp32", False),
+                "c4": (64, "fp32", True), "c5": (64, "fp32", True)}[args.config]
+    B = args.B or defaults[0]
+    precision = args.precision or defaults[1]
+    grad = defaults[2] and not args.forward_only
     t0 = time.time()
     cat = synth.make_catalog(args.config)
     print(f"# generated {args.config}: {cat.n_events} events, {cat.n_pix} pixels, {cat.n_samp} samples, "
           f"{cat.n_inj} injections, LOS {cat.los.nbytes / 1e9:.2f} GB in {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
     t0 = time.time()
-    lik = binding.DarkSirenLikelihood(cat, precision="fp32")
+    lik = binding.DarkSirenLikelihood(cat, precision=precision)
     print(f"# uploaded in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    B = args.B
     lam_np = synth.lambdas_for(args.config, B)
     lam = torch.tensor(lam_np, device="cuda:0")
-    if args.autotune:
+    if not args.no_autotune:
+        t0 = time.time()
         lik.autotune(B, grad)
+        print(f"# autotuned in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     dev = lam.device
     logL = torch.empty(B, dtype=torch.float64, device=dev)
     g = torch.empty(B, 16, dtype=torch.float64, device=dev)
@@ -144,16 +152,19 @@ def main():
     F = FLOP_PER_WEIGHT_GRAD if grad else FLOP_PER_WEIGHT_FWD
     flops = F * n_w * B
     achieved = flops / (sweep_avg * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-                "kernel": "sweep_kernel<float,64,%s>" % ("true" if grad else "false"),
+    peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
+                                                       int(lik.info("lambda_tile_used")), "true" if grad else "false"),
                 "kernel_ms": round(sweep_avg, 4),
                 "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
-                "flop_per_weight": F, "weights_per_launch": n_w * B}
+                "flop_per_weight": F, "weights_per_launch": n_w * B,
+                "chunk": int(lik.info("chunk")), "items": int(lik.info("n_items"))}
 
     # one-Lambda-per-launch comparison (same kernels, B = 1, 64 launches)
     single = None
-    if not args.no_single:
+    if not args.no_single and B > 1:
         lam1 = lam[:1].contiguous()
         out1 = torch.empty(1, dtype=torch.float64, device=dev)
         g1 = torch.empty(1, 16, dtype=torch.float64, device=dev)
@@ -182,20 +193,23 @@ def main():
                   "speedup_batched_vs_single": round((single_s / B) / (ms_per_step / 1e3 / B), 2)}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.config in ("c4", "c2"):
         cpu = cpu_baseline(cat, lam_np[0], grad)
 
     res = {
-        "metric": "Lambda-evaluations/sec (log L + grad) on O5-like catalogue" if grad
-        else "Lambda-evaluations/sec (log L) on O5-like catalogue",
+        "metric": ("Lambda-evaluations/sec (log L + grad) on O5-like catalogue" if grad
+                   else "Lambda-evaluations/sec (log L) on O5-like catalogue") if args.config == "c4"
+        else "Lambda-evaluations/sec (log L%s), workload %s" % (" + grad" if grad else "", args.config),
         "value": round(value, 3), "unit": "Lambda-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "O5-like batched (c4): %d events, U[1000,8192] samples/event (%d total), "
-                               "32-2048 pixels/event x %d-node LOS tables (%.2f GB), %d injections, "
-                               "%d Lambda per launch, ln L + d ln L/d Lambda (16 entries)"
-                               % (cat.n_events, cat.n_samp, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B),
-                   "B": B, "precision": "FP32 weights, FP64 sums"},
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d events, %d samples, %d pixels x %d-node LOS tables (%.2f GB), %d injections, "
+                               "%d Lambda per launch, %s"
+                               % ({"c4": "O5-like batched (c4)"}.get(args.config, args.config), cat.n_events,
+                                  cat.n_samp, cat.n_pix, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B,
+                                  "ln L + d ln L/d Lambda (16 entries)" if grad else "ln L"),
+                   "B": B, "precision": "FP32 weights, FP64 sums" if precision == "fp32" else "FP64"},
         "gsample_weights_per_s": round(n_w * B * args.steps / wall / 1e9, 3),
         "kernel_ms": {"setup": round(float(np.mean(setup_ms)), 4), "sweep": round(sweep_avg, 4),
                       "combine": round(float(np.mean(comb_ms)), 4)},

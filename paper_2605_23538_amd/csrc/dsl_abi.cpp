@@ -24,9 +24,10 @@ size_t sweep_lds_bytes(int fp32, int GL, bool grad);
 hipError_t launch_pack(int fp32, const double* m1, const double* m2, const double* dl, const double* lnp,
                        int64_t n, void* out, hipStream_t st);
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, hipStream_t st);
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st);
 hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
+hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
 hipError_t init_kernel_attrs();
 }  // namespace dsl
 
@@ -106,10 +107,10 @@ struct dsl_handle {
   DevBuf samp, inj, pix_off, pix_row, los, sky, ln_ns;
   // work list (for the current chunk size)
   int64_t built_chunk = -1;
-  DevBuf items, order, ev_item_off;
-  int n_items = 0, inj_slot0 = 0, inj_slot1 = 0;
+  DevBuf items, order, ev_item_off, splits;
+  int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -118,6 +119,7 @@ struct dsl_handle {
   int64_t chunk_opt = 0;
   int timing = 0;
   int graph = 1;
+  int last_gl = 0;           // Lambda tile of the last call
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool have_timing = false;
   hipStream_t cap_stream = nullptr;
@@ -187,7 +189,7 @@ int validate(const dsl_catalog_desc* d) {
 int upload(DevBuf& b, const void* src, size_t bytes) {
   hipError_t e = b.ensure(bytes);
   if (e != hipSuccess) return fail(DSL_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  if (bytes && src) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
   return DSL_OK;
 }
 
@@ -215,10 +217,13 @@ int pack_samples(dsl_handle* h, DevBuf& out, const double* m1, const double* m2,
   return DSL_OK;
 }
 
-int64_t auto_chunk(const dsl_handle* h) {
+// Target samples per work item: about 16 items per CU for one-point tiles
+// (a wavefront then sweeps 64 samples per step), 64 per CU otherwise.
+int64_t auto_chunk(const dsl_handle* h, int GL) {
   const int64_t total = h->n_samp + h->n_inj;
-  int64_t c = total / ((int64_t)h->n_cu * 64);
-  return std::max<int64_t>(64, std::min<int64_t>(16384, c));
+  const int64_t per_cu = GL == 1 ? 16 : 64;
+  int64_t c = total / ((int64_t)h->n_cu * per_cu);
+  return std::max<int64_t>(GL == 1 ? 256 : 64, std::min<int64_t>(16384, c));
 }
 
 // Work list: runs of whole pixels of one event (about `chunk` samples each; a
@@ -227,15 +232,36 @@ int64_t auto_chunk(const dsl_handle* h) {
 int build_items(dsl_handle* h, int64_t chunk) {
   if (chunk == h->built_chunk) return DSL_OK;
   std::vector<WorkItem> it;
+  std::vector<SplitPix> sp;
   std::vector<int32_t> ev_off(h->n_events + 1, 0);
+  // pixels with more than 2 chunks of samples are split into parts of one chunk
+  const int64_t split_thr = 2 * chunk;
   for (int64_t e = 0; e < h->n_events; ++e) {
     ev_off[e] = (int32_t)it.size();
     const int64_t p0 = h->epo[e], p1 = h->epo[e + 1];
     int64_t a = p0;
     while (a < p1) {
+      if (h->pso[a + 1] - h->pso[a] > split_thr) {
+        SplitPix s;
+        s.slot0 = (int32_t)it.size();
+        s.n_parts = 0;
+        for (int64_t x = h->pso[a]; x < h->pso[a + 1]; x += chunk) {
+          WorkItem w;
+          w.event = (int32_t)e;
+          w.pix0 = w.pix1 = (int32_t)a;
+          w.slot = (int32_t)it.size();
+          w.s0 = x;
+          w.s1 = std::min(h->pso[a + 1], x + chunk);
+          it.push_back(w);
+          ++s.n_parts;
+        }
+        sp.push_back(s);
+        ++a;
+        continue;
+      }
       int64_t b = a + 1;
       int64_t n = h->pso[b] - h->pso[a];
-      while (b < p1 && n + (h->pso[b + 1] - h->pso[b]) <= chunk) {
+      while (b < p1 && n + (h->pso[b + 1] - h->pso[b]) <= chunk && h->pso[b + 1] - h->pso[b] <= split_thr) {
         n += h->pso[b + 1] - h->pso[b];
         ++b;
       }
@@ -269,6 +295,12 @@ int build_items(dsl_handle* h, int64_t chunk) {
   if ((rc = upload(h->items, it.data(), it.size() * sizeof(WorkItem)))) return rc;
   if ((rc = upload(h->order, ord.data(), ord.size() * sizeof(int32_t)))) return rc;
   if ((rc = upload(h->ev_item_off, ev_off.data(), ev_off.size() * sizeof(int32_t)))) return rc;
+  if (sp.empty()) {
+    if (h->splits.ensure(sizeof(SplitPix)) != hipSuccess) return fail(DSL_ENOMEM, "hipMalloc splits");
+  } else if ((rc = upload(h->splits, sp.data(), sp.size() * sizeof(SplitPix)))) {
+    return rc;
+  }
+  h->n_split = (int)sp.size();
   h->n_items = (int)it.size();
   h->inj_slot0 = inj0;
   h->inj_slot1 = (int)it.size();
@@ -294,7 +326,7 @@ SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   if (h->lambda_tile) c.GL = h->lambda_tile;
   if (!h->fp32 && c.GL > 4) c.GL = 4;
   if (h->chunk_opt) c.chunk = h->chunk_opt;
-  if (c.chunk <= 0) c.chunk = auto_chunk(h);
+  if (c.chunk <= 0) c.chunk = auto_chunk(h, c.GL);
   return c;
 }
 
@@ -309,6 +341,7 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
   const int NWG = h->fp32 ? NWG_F32 : NWG_F64;
   if ((e = h->wg_tab.ensure(6 * t1 * (NWG + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (wg)");
   if ((e = h->valid.ensure(sizeof(int) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (valid)");
+  if ((e = h->gmap.ensure(sizeof(double) * N_GMAP * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (gmap)");
   const size_t nf = grad ? NF_GRAD : NF_FWD;
   if ((e = h->part.ensure(sizeof(double) * nf * (size_t)B * std::max(h->n_items, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (partials)");
@@ -329,7 +362,8 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
             hipStream_t st, bool timed) {
   if (timed) HIPCHK(hipEventRecord(h->ev[0], st));
   HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, h->lamc.p, h->cos_tab.p, h->win_tab.p,
-                      grad ? h->wg_tab.p : nullptr, h->valid.as<int>(), st));
+                      grad ? h->wg_tab.p : nullptr, h->valid.as<int>(), grad ? h->gmap.as<double>() : nullptr,
+                      st));
   if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
   SweepArgs a;
   a.samp = h->samp.p;
@@ -356,6 +390,15 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   int grid_x = std::max(1, (h->n_cu * cfg.wg_per_cu + n_tiles - 1) / n_tiles);
   grid_x = std::min(grid_x, std::max(1, (h->n_items + waves - 1) / waves));
   HIPCHK(launch_sweep(h->fp32, cfg.GL, grad, a, grid_x, 64 * waves, st));
+  GateSplitArgs gs;
+  gs.part = h->part.as<double>();
+  gs.nf = grad ? NF_GRAD : NF_FWD;
+  gs.B = B;
+  gs.splits = h->splits.as<SplitPix>();
+  gs.n_split = h->n_split;
+  gs.neff_min = h->neff_min;
+  gs.gate_mode = h->gate_mode;
+  HIPCHK(launch_gate_split(gs, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[2], st));
   CombineArgs c;
   c.part = h->part.as<double>();
@@ -376,6 +419,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.neff_sel = o.neff_sel;
   c.flags = o.flags;
   c.grad = o.grad;
+  c.gmap = h->gmap.as<double>();
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -383,12 +427,14 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
 
 int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& o, hipStream_t st) {
   if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  (void)hipGetLastError();   // the launch checks below must not see an earlier call's error
   if (!d_lambda || !o.logL || (grad && !o.grad)) return fail(DSL_EINVAL, "NULL device pointer");
   if (B < 1 || B > h->max_batch) return fail(DSL_EINVAL, "B out of range [1, max_batch]");
   int cur = -1;
   HIPCHK(hipGetDevice(&cur));
   if (cur != h->device) return fail(DSL_ESTATE, "current device differs from the handle's device");
   const SweepCfg cfg = config_for(h, B, grad);
+  h->last_gl = cfg.GL;
   int rc;
   if ((rc = build_items(h, cfg.chunk))) return rc;
   if ((rc = ensure_workspace(h, B, grad))) return rc;
@@ -444,6 +490,7 @@ int dsl_create(const dsl_catalog_desc* d, dsl_handle** out) {
   if (rc) return rc;
   std::unique_ptr<dsl_handle> h(new (std::nothrow) dsl_handle());
   if (!h) return fail(DSL_ENOMEM, "host allocation");
+  (void)hipGetLastError();
   HIPCHK(hipGetDevice(&h->device));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, h->device));
@@ -526,13 +573,15 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "n_draw") *v = (double)h->n_draw;
   else if (k == "n_z") *v = (double)h->n_z;
   else if (k == "n_items") *v = (double)h->n_items;
+  else if (k == "n_split") *v = (double)h->n_split;
   else if (k == "precision") *v = h->fp32 ? DSL_PRECISION_FP32 : DSL_PRECISION_FP64;
   else if (k == "neff_min") *v = h->neff_min;
   else if (k == "gate_mode") *v = h->gate_mode;
   else if (k == "max_batch") *v = h->max_batch;
   else if (k == "lambda_tile") *v = h->lambda_tile;
-  else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : auto_chunk(h));
+  else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
   else if (k == "n_cu") *v = h->n_cu;
+  else if (k == "lambda_tile_used") *v = h->last_gl;
   else if (k == "device_bytes") {
     *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
                   h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n);
@@ -597,8 +646,7 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
   }
   // candidates
   std::vector<int> gls = h->fp32 ? std::vector<int>{1, 4, 16, 64} : std::vector<int>{1, 4};
-  const int64_t base = auto_chunk(h);
-  std::vector<int64_t> chunks = {std::max<int64_t>(64, base / 4), base, std::min<int64_t>(65536, base * 4)};
+
   // scratch Lambda batch: the prior's centre replicated (valid everywhere)
   std::vector<double> lam(16 * (size_t)B);
   const double centre[16] = {70, 0.3, 2.9, 1.0, 4.6, 86.3, 4.8, 9.7, 0.7, 30.7, 6.3, 0.4, 0.8, 3.3, 2.9, 2.5};
@@ -623,6 +671,8 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
   HIPCHK(hipEventCreate(&e1));
   for (int gl : gls) {
     if (gl > 1 && B < gl / 4) continue;   // mostly idle lanes
+    const int64_t base = auto_chunk(h, gl);
+    const std::vector<int64_t> chunks = {std::max<int64_t>(64, base / 4), base, std::min<int64_t>(65536, base * 4)};
     for (int64_t ch : chunks) {
       SweepCfg c;
       c.GL = gl;

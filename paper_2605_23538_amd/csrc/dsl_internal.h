@@ -58,13 +58,23 @@ struct LamC {
 
 // Number of window-derivative tables used by the adjoint (beta, m_min, delta_m).
 constexpr int N_WIN_GRAD = 3;
+// Per-point FP64 coefficients that map the adjoint's 16 basis sums to the
+// gradient (written by setup, applied by combine).
+constexpr int N_GMAP = 24;
 
-// Work item: a run of whole pixels of one event, or a run of injections.
+// Work item: a run of whole pixels of one event, a part of one large pixel
+// (pix1 == pix0: samples [s0, s1) of pixel pix0, written ungated), or a run of
+// injections (event == -1).
 struct WorkItem {
   int32_t event;     // >= 0: event index; -1: injection chunk
   int32_t pix0, pix1;
   int32_t slot;      // row of the partial-result buffer
   int64_t s0, s1;    // sample (or injection) range
+};
+
+// A pixel split over several consecutive slots; merged and gated before combine.
+struct SplitPix {
+  int32_t slot0, n_parts;
 };
 
 // Packed sample (the sweep's input record), precision T.
@@ -104,6 +114,16 @@ struct SweepArgs {
   double* part;              // [n_items][NF][B]
 };
 
+struct GateSplitArgs {
+  double* part;
+  int32_t nf;
+  int32_t B;
+  const SplitPix* splits;
+  int32_t n_split;
+  double neff_min;
+  int32_t gate_mode;
+};
+
 struct CombineArgs {
   const double* part;
   int32_t nf;                // NF_FWD or NF_GRAD
@@ -122,6 +142,7 @@ struct CombineArgs {
   double* neff_sel;             // [B] or null
   uint32_t* flags;              // [B] or null
   double* grad;                 // [B][16] or null
+  const double* gmap;           // [B][N_GMAP] (adjoint only)
 };
 
 }  // namespace dsl

@@ -59,20 +59,6 @@ __constant__ double GL8_W[8] = {0.1012285362903763, 0.2223810344533745, 0.313706
                                 0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
                                 0.2223810344533745, 0.1012285362903763};
 
-// I(z) = int_0^z dz'/E(z') by composite 8-point Gauss-Legendre (8 panels).
-__device__ double comoving_I(double z, double Om) {
-  const int P = 8;
-  const double h = z / P;
-  double acc = 0.0;
-  for (int p = 0; p < P; ++p) {
-    const double c = (p + 0.5) * h;
-    double s = 0.0;
-    for (int k = 0; k < 8; ++k) s += GL8_W[k] / E_of(c + 0.5 * h * GL8_X[k], Om);
-    acc += 0.5 * h * s;
-  }
-  return acc;
-}
-
 // Smoothing window S(m) and its logarithmic derivatives (x = m - m_min).
 struct SmoothD {
   double S, omS;   // S and 1 - S
@@ -112,7 +98,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
                                                     typename V2<T>::t* __restrict__ cos_tab,
                                                     typename V2<T>::t* __restrict__ win_tab,
                                                     typename V2<T>::t* __restrict__ win_grad_tab,
-                                                    int* __restrict__ valid_out) {
+                                                    int* __restrict__ valid_out, double* __restrict__ gmap) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW, NWG = Tab<T>::NWG;
   const int b = blockIdx.x;
@@ -133,8 +119,36 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   const double M = mmin + dm;
   const double s = beta + 1.0;
 
+  // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
+  constexpr int KZ = 256;
+  __shared__ double Itab[KZ + 1];
+  const double hz = z_max / KZ;
+  for (int k = tid; k < KZ; k += blockDim.x) {
+    double sacc = 0.0;
+    if (ok) {
+      const double c = (k + 0.5) * hz;
+      for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(c + 0.5 * hz * GL8_X[q], Om);
+      sacc *= 0.5 * hz;
+    }
+    Itab[k + 1] = sacc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Itab[0] = 0.0;
+    for (int k = 1; k <= KZ; ++k) Itab[k] += Itab[k - 1];
+  }
+  __syncthreads();
+  // I(z) = Itab[k] + 8-point Gauss-Legendre over [z_k, z]
+  auto I_at = [&](double z) {
+    int k = (int)(z / hz);
+    k = k < 0 ? 0 : (k > KZ - 1 ? KZ - 1 : k);
+    const double a = k * hz, h = z - a;
+    double sacc = 0.0;
+    for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(a + 0.5 * h * (GL8_X[q] + 1.0), Om);
+    return Itab[k] + 0.5 * h * sacc;
+  };
   // --- inverse distance table: y(v) = z/u at v_k = 1 + k h_v, u = (v^2-1)/4.
-  const double umax = ok ? (1.0 + z_max) * comoving_I(z_max, Om) : 1.0;
+  const double umax = ok ? (1.0 + z_max) * Itab[KZ] : 1.0;
   const double vmax = sqrt(1.0 + 4.0 * umax);
   const double hv = (vmax - 1.0) / NU;
   for (int k = tid; k <= NU; k += blockDim.x) {
@@ -143,18 +157,25 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
       const double dv = k * hv;
       const double u = dv * (2.0 + dv) * 0.25;
       const double v = 1.0 + dv;
-      double z = 2.0 * u / (1.0 + v), lo = 0.0, hi = z_max * 1.0000001;
-      for (int it = 0; it < 40; ++it) {
-        const double I = comoving_I(z, Om);
+      // bracket: the panel [z_j, z_j+1] with D(z_j) <= u <= D(z_j+1), D = (1+z) I
+      int lo = 0, hi = KZ;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((1.0 + mid * hz) * Itab[mid] <= u) lo = mid; else hi = mid;
+      }
+      const double za = lo * hz, zb = hi * hz;
+      const double Da = (1.0 + za) * Itab[lo], Db = (1.0 + zb) * Itab[hi];
+      double z = za + (zb - za) * (u - Da) / (Db - Da);
+      for (int it = 0; it < 12; ++it) {
+        const double I = I_at(z);
         const double f = (1.0 + z) * I - u;
-        if (f > 0) hi = z; else lo = z;
         double zn = z - f / (I + (1.0 + z) / E_of(z, Om));
-        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
-        const bool done = fabs(zn - z) <= 1e-14 * z;
+        zn = fmin(fmax(zn, za), zb);
+        const bool done = fabs(zn - z) <= 4e-16 * zn;
         z = zn;
         if (done) break;
       }
-      const double I = comoving_I(z, Om);
+      const double I = I_at(z);
       const double zp_u = 1.0 / (I + (1.0 + z) / E_of(z, Om));
       y = z / u;
       dy = (zp_u * u - z) / (u * u) * (0.5 * v);
@@ -351,6 +372,33 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     c.valid = ok ? 1 : 0;
     lamc[b] = c;
     valid_out[b] = c.valid;
+    if (gmap) {
+      double* gm = gmap + (size_t)b * N_GMAP;
+      gm[0] = 1.0 / H0;
+      gm[1] = dbPa;
+      gm[2] = dbPmin;
+      gm[3] = dLlo;
+      gm[4] = dHlo;
+      gm[5] = dbPmax;
+      gm[6] = dLhi;
+      gm[7] = dHhi;
+      gm[8] = dLmu;
+      gm[9] = dLsg;
+      gm[10] = dHmu;
+      gm[11] = dHsg;
+      gm[12] = 1.0 / (sL * sL);
+      gm[13] = 1.0 / (sL * sL * sL);
+      gm[14] = 1.0 / (sH * sH);
+      gm[15] = 1.0 / (sH * sH * sH);
+      gm[16] = lg < 1 ? 1.0 / (1.0 - lg) : 0.0;
+      gm[17] = lg > 0 ? 1.0 / lg : 0.0;
+      gm[18] = ll > 0 ? 1.0 / ll : 0.0;
+      gm[19] = ll < 1 ? 1.0 / (1.0 - ll) : 0.0;
+      gm[20] = (gam + kap) / (1.0 + zp);
+      gm[21] = LN2;
+      gm[22] = 0.0;
+      gm[23] = 0.0;
+    }
   }
 }
 
@@ -550,9 +598,6 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     }
     const T dDp_dOm = dI_dOm - (T)0.5 * opz * (opz * opz * opz - (T)1) * rE * rE * rE;
     const T dz_dOm = -opz * dI_dOm * rDp;
-    g[0] = c.inv_H0 + Gz * dz_dH0;
-    g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
-    g[2] = fP * (c.dbP_alpha - lnm1);
     // beta: ln q - (d rho / d beta) / rho
     T drho_b, drho_mmin, drho_dm;
     if (inwin) {
@@ -576,30 +621,37 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       drho_mmin = c.zw_mmin * Em;
       drho_dm = c.zw_dm * Em;
     }
-    g[3] = lnq - drho_b * rrho;
-    g[4] = fP * c.dbP_mmin + fL * c.dbL_mmin + fH * c.dbH_mmin - dlnS2_dm - drho_mmin * rrho;
-    g[5] = fP * c.dbP_mmax + fL * c.dbL_mmax + fH * c.dbH_mmax;
-    g[6] = dlnS2_ddm - drho_dm * rrho;
-    g[7] = fL * (c.dbL_mu + dLo * c.isL2);
-    g[8] = fL * (c.dbL_sig + dLo * dLo * c.isL3);
-    g[9] = fH * (c.dbH_mu + dHi * c.isH2);
-    g[10] = fH * (c.dbH_sig + dHi * dHi * c.isH3);
-    g[11] = -fP * c.aPg + (fL + fH) * c.aLg;
-    g[12] = fL * c.aLl - fH * c.aHl;
-    g[13] = L * ln2 - sig * lratio;
-    g[14] = -sig * lratio;
-    g[15] = sig * c.gk * c.inv_opzp;
+    // Basis terms: d ln w / d Lambda_p = sum_j C_pj(Lambda) b_j (+ 1/H0 for H0);
+    // the per-point coefficients C are applied once per point in combine_kernel.
+    g[0] = Gz * dz_dH0;
+    g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
+    g[2] = fP;
+    g[3] = fP * lnm1;
+    g[4] = lnq - drho_b * rrho;
+    g[5] = fL;
+    g[6] = fH;
+    g[7] = dlnS2_dm + drho_mmin * rrho;
+    g[8] = dlnS2_ddm - drho_dm * rrho;
+    g[9] = fL * dLo;
+    g[10] = g[9] * dLo;
+    g[11] = fH * dHi;
+    g[12] = g[11] * dHi;
+    g[13] = L;
+    g[14] = sig * lratio;
+    g[15] = sig;
   }
 }
 
 // ---------------------------------------------------------------------------
-// exponent-tracked FP64 accumulation
+// exponent-tracked accumulation
 // ---------------------------------------------------------------------------
-template <bool GRAD>
-struct Acc {
+// Pixel-level sums: S1 = sum w, S2 = sum w^2 in FP64, and (adjoint) the 16
+// basis sums sum w b_j in BT (FP32 for the FP32 sweep), all scaled by 2^-R.
+template <bool GRAD, typename BT>
+struct PixAcc {
   int R;
   double S1, S2;
-  double G[GRAD ? 16 : 1];
+  BT G[GRAD ? 16 : 1];
   __device__ __forceinline__ void zero() {
     R = R_SENTINEL;
     S1 = 0;
@@ -617,18 +669,6 @@ struct Acc {
     }
     R = Rn;
   }
-  // add another accumulator (values scaled by 2^o.R)
-  __device__ __forceinline__ void merge(const Acc& o) {
-    const int Rm = R > o.R ? R : o.R;
-    const int da = R - Rm, db = o.R - Rm;
-    S1 = ldexp(S1, da) + ldexp(o.S1, db);
-    S2 = ldexp(S2, 2 * da) + ldexp(o.S2, 2 * db);
-    if constexpr (GRAD) {
-#pragma unroll
-      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], da) + ldexp(o.G[p], db);
-    }
-    R = Rm;
-  }
   template <typename T>
   __device__ __forceinline__ void add(int n, T lin, const T* g) {
     if (lin > (T)0) {
@@ -638,21 +678,54 @@ struct Acc {
       S1 += W;
       S2 = fma(W, W, S2);
       if constexpr (GRAD) {
+        const BT Wb = ldexp((BT)lin, n - R);
 #pragma unroll
-        for (int p = 0; p < 16; ++p) G[p] = fma(W, (double)g[p], G[p]);
+        for (int p = 0; p < 16; ++p) G[p] = fma(Wb, (BT)g[p], G[p]);
       }
     }
   }
   __device__ __forceinline__ void xor_merge(int off) {
-    Acc o;
-    o.R = __shfl_xor(R, off);
-    o.S1 = __shfl_xor(S1, off);
-    o.S2 = __shfl_xor(S2, off);
+    const int Ro = __shfl_xor(R, off);
+    const double S1o = __shfl_xor(S1, off), S2o = __shfl_xor(S2, off);
+    const int Rm = R > Ro ? R : Ro;
+    const int da = R - Rm, db = Ro - Rm;
+    S1 = ldexp(S1, da) + ldexp(S1o, db);
+    S2 = ldexp(S2, 2 * da) + ldexp(S2o, 2 * db);
     if constexpr (GRAD) {
 #pragma unroll
-      for (int p = 0; p < 16; ++p) o.G[p] = __shfl_xor(G[p], off);
+      for (int p = 0; p < 16; ++p) {
+        const BT o = __shfl_xor(G[p], off);
+        G[p] = ldexp(G[p], da) + ldexp(o, db);
+      }
     }
-    merge(o);
+    R = Rm;
+  }
+};
+
+// Item-level sums (FP64 throughout).
+template <bool GRAD>
+struct ItemAcc {
+  int R;
+  double S1, S2;
+  double G[GRAD ? 16 : 1];
+  __device__ __forceinline__ void zero() {
+    R = R_SENTINEL;
+    S1 = 0;
+    S2 = 0;
+#pragma unroll
+    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+  }
+  template <typename BT>
+  __device__ __forceinline__ void merge(const PixAcc<GRAD, BT>& o) {
+    const int Rm = R > o.R ? R : o.R;
+    const int da = R - Rm, db = o.R - Rm;
+    S1 = ldexp(S1, da) + ldexp(o.S1, db);
+    S2 = ldexp(S2, 2 * da) + ldexp(o.S2, 2 * db);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], da) + ldexp((double)o.G[p], db);
+    }
+    R = Rm;
   }
 };
 
@@ -672,10 +745,10 @@ __device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_
 
 // One run of samples [s0, s1) accumulated into acc; the next record is
 // loaded while the current one is evaluated.
-template <typename T, int GL, bool GRAD>
+template <typename T, int GL, bool GRAD, typename AccT>
 __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
                                           bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
-                                          const float* __restrict__ tab, int n_z, T inv_dz, Acc<GRAD>& acc,
+                                          const float* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
                                           T* g) {
   constexpr int NS = 64 / GL;
   if (s1 <= s0) return;
@@ -747,14 +820,23 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
 
   for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
     const WorkItem w = a.items[a.order[it]];
-    Acc<GRAD> chunk;
+    ItemAcc<GRAD> chunk;
     chunk.zero();
     int npass = 0;
-    if (w.event >= 0) {
+    if (w.event >= 0 && w.pix1 == w.pix0) {
+      // part of a large pixel: ungated sums, gated after the sweep (gate_split_kernel)
+      const float* __restrict__ tab = a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
+      PixAcc<GRAD, T> pix;
+      pix.zero();
+      sweep_run<T, GL, GRAD>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
+#pragma unroll
+      for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
+      chunk.merge(pix);
+    } else if (w.event >= 0) {
       for (int p = w.pix0; p < w.pix1; ++p) {
         const int64_t s0 = a.pix_off[p], s1 = a.pix_off[p + 1];
         const float* __restrict__ tab = a.los + (size_t)a.pix_row[p] * a.n_z;
-        Acc<GRAD> pix;
+        PixAcc<GRAD, T> pix;
         pix.zero();
         sweep_run<T, GL, GRAD>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
 #pragma unroll
@@ -768,9 +850,17 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         }
       }
     } else {
-      sweep_run<T, GL, GRAD>(inj, w.s0, w.s1, sg, live, c, tv, lam, a.sky, a.n_z, inv_dz, chunk, g);
+      // injections in runs of 256 per lane (the pixel-level sums are FP32 for the adjoint)
+      constexpr int64_t VP = 256 * (64 / GL);
+      for (int64_t v0 = w.s0; v0 < w.s1; v0 += VP) {
+        PixAcc<GRAD, T> pix;
+        pix.zero();
+        const int64_t v1 = v0 + VP < w.s1 ? v0 + VP : w.s1;
+        sweep_run<T, GL, GRAD>(inj, v0, v1, sg, live, c, tv, lam, a.sky, a.n_z, inv_dz, pix, g);
 #pragma unroll
-      for (int off = GL; off < 64; off <<= 1) chunk.xor_merge(off);
+        for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
+        chunk.merge(pix);
+      }
     }
     if (sg == 0 && active) {
       double* out = a.part + (size_t)w.slot * NF * a.B + b;
@@ -783,6 +873,51 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         for (int p = 0; p < 16; ++p) out[(size_t)(4 + p) * a.B] = chunk.G[p];
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gate of split pixels: merge the parts (in slot order), apply Eq. (8), write
+// the result into the first part's slot and clear the others.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gate_split_kernel(GateSplitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.n_split * a.B) return;
+  const int sp = (int)(i / a.B), b = (int)(i % a.B);
+  const SplitPix s = a.splits[sp];
+  auto at = [&](int slot, int f) -> double& { return a.part[((size_t)slot * a.nf + f) * a.B + b]; };
+  double R = -1e300, S1 = 0, S2 = 0;
+  double G[16];
+  for (int p = 0; p < 16; ++p) G[p] = 0;
+  const int ng = a.nf - 4;
+  for (int k = 0; k < s.n_parts; ++k) {
+    const int sl = s.slot0 + k;
+    const double s1 = at(sl, 1);
+    if (!(s1 > 0)) continue;
+    const double r = at(sl, 0);
+    if (r > R) {
+      const int d = (R > -1e299) ? (int)(R - r) : -2000;
+      S1 = ldexp(S1, d);
+      S2 = ldexp(S2, 2 * d);
+      for (int p = 0; p < ng; ++p) G[p] = ldexp(G[p], d);
+      R = r;
+    }
+    const int d = (int)(r - R);
+    S1 += ldexp(s1, d);
+    S2 += ldexp(at(sl, 2), 2 * d);
+    for (int p = 0; p < ng; ++p) G[p] += ldexp(at(sl, 4 + p), d);
+  }
+  bool pass;
+  if (a.gate_mode == 2) pass = S1 > 0;
+  else pass = S2 > 0 && S1 * S1 >= a.neff_min * S2;
+  for (int k = 0; k < s.n_parts; ++k) {
+    const int sl = s.slot0 + k;
+    const bool first = k == 0 && pass;
+    at(sl, 0) = first ? R : (double)R_SENTINEL;
+    at(sl, 1) = first ? S1 : 0.0;
+    at(sl, 2) = first ? S2 : 0.0;
+    at(sl, 3) = first ? 1.0 : 0.0;
+    for (int p = 0; p < ng; ++p) at(sl, 4 + p) = first ? G[p] : 0.0;
   }
 }
 
@@ -817,6 +952,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   __shared__ unsigned int fl[256];
   __shared__ Part3 rp[256];
   double acc = 0;
+  double n_ev_used = 0;
   double accg[GRAD ? 16 : 1];
 #pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) accg[p] = 0;
@@ -827,6 +963,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
 #pragma unroll
     for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
     double Rg = -1e300;
+#pragma unroll 4
     for (int sl = a.ev_item_off[e]; sl < a.ev_item_off[e + 1]; ++sl) {
       Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
       if constexpr (GRAD) {
@@ -860,6 +997,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
       if (m.S1 > 0) {
         // G and S1 share the scale 2^m.R (Rg == m.R)
         for (int p = 0; p < 16; ++p) accg[p] += G[p] / m.S1;
+        n_ev_used += 1.0;
       }
     }
   }
@@ -869,6 +1007,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   double Rgs = -1e300;
 #pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) Gs[p] = 0;
+#pragma unroll 4
   for (int sl = a.inj_slot0 + tid; sl < a.inj_slot1; sl += blockDim.x) {
     Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
     if constexpr (GRAD) {
@@ -884,6 +1023,8 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   }
   red[tid] = acc;
   fl[tid] = flags;
+  __shared__ double nused[256];
+  nused[tid] = n_ev_used;
   rp[tid] = sel;
   if constexpr (GRAD) {
     for (int p = 0; p < 16; ++p) redg[p][tid] = accg[p];
@@ -892,6 +1033,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   for (int st = 128; st > 0; st >>= 1) {
     if (tid < st) {
       red[tid] += red[tid + st];
+      nused[tid] += nused[tid + st];
       fl[tid] |= fl[tid + st];
       if constexpr (GRAD) {
         for (int p = 0; p < 16; ++p) redg[p][tid] += redg[p][tid + st];
@@ -951,10 +1093,29 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     if (a.flags) a.flags[b] = f;
     if constexpr (GRAD) {
       if (a.grad) {
-        for (int p = 0; p < 16; ++p) {
-          const double gv = (f == 0) ? redg[p][0] - (double)a.n_events * gsel[p][0] / s.S1 : 0.0;
-          a.grad[(size_t)b * 16 + p] = gv;
-        }
+        // basis totals T_j = sum_i B_ij / S1_i - N_det B_sel,j / S1_sel, then the map
+        double T[16];
+        for (int p = 0; p < 16; ++p) T[p] = (f == 0) ? redg[p][0] - (double)a.n_events * gsel[p][0] / s.S1 : 0.0;
+        const double* c = a.gmap + (size_t)b * N_GMAP;
+        const double T1 = nused[0] - (double)a.n_events;   // coefficient of the constant 1/H0 term
+        double g[16];
+        g[0] = c[0] * T1 + T[0];
+        g[1] = T[1];
+        g[2] = c[1] * T[2] - T[3];
+        g[3] = T[4];
+        g[4] = c[2] * T[2] + c[3] * T[5] + c[4] * T[6] - T[7];
+        g[5] = c[5] * T[2] + c[6] * T[5] + c[7] * T[6];
+        g[6] = T[8];
+        g[7] = c[8] * T[5] + c[12] * T[9];
+        g[8] = c[9] * T[5] + c[13] * T[10];
+        g[9] = c[10] * T[6] + c[14] * T[11];
+        g[10] = c[11] * T[6] + c[15] * T[12];
+        g[11] = -c[16] * T[2] + c[17] * (T[5] + T[6]);
+        g[12] = c[18] * T[5] - c[19] * T[6];
+        g[13] = c[21] * T[13] - T[14];
+        g[14] = -T[14];
+        g[15] = c[20] * T[15];
+        for (int p = 0; p < 16; ++p) a.grad[(size_t)b * 16 + p] = (f == 0) ? g[p] : 0.0;
       }
     }
   }
@@ -1003,13 +1164,13 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 }
 
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, hipStream_t st) {
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st) {
   if (fp32)
     setup_kernel<float><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
-                                            (float2*)win_tab, (float2*)win_grad_tab, valid);
+                                            (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
   else
     setup_kernel<double><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
-                                             (double2*)win_tab, (double2*)win_grad_tab, valid);
+                                             (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
   return hipGetLastError();
 }
 
@@ -1058,6 +1219,13 @@ hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int gri
   }
 #undef DSL_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
+  if (a.n_split == 0) return hipSuccess;
+  const int64_t n = (int64_t)a.n_split * a.B;
+  gate_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
