@@ -32,6 +32,11 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GH
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated against
+# an elementwise copy of known size; profiles/sweep_c4_grad_traffic.txt), valid only for
+# the kernel source they were measured on.
+MEASURED_TRAFFIC = {("c4", 64, True): {"kernel_sha256_16": "ed407937d8956280", "bytes": 5.113e9}}
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -45,7 +50,16 @@ def parse():
     p.add_argument("--no-single", action="store_true", help="skip the one-Lambda-per-launch comparison")
     p.add_argument("--no-autotune", action="store_true", help="use the default tile shape and chunk")
     p.add_argument("--forward-only", action="store_true")
+    p.add_argument("--copy-calib", type=int, default=0,
+                   help="after the timed steps, run one elementwise copy of this many MiB (calibrates "
+                        "rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
     return p.parse_args()
+
+
+def kernel_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2605_23538_amd", "csrc", "dsl_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def cpu_baseline(cat, lam_row, grad):
@@ -153,8 +167,12 @@ def main():
     flops = F * n_w * B
     achieved = flops / (sweep_avg * 1e-3) / 1e12
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
+    traffic = None
+    mt = MEASURED_TRAFFIC.get((args.config, B, grad))
+    if mt and precision == "fp32" and kernel_sha() == mt["kernel_sha256_16"]:
+        traffic = mt["bytes"]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
                                                        int(lik.info("lambda_tile_used")), "true" if grad else "false"),
                 "kernel_ms": round(sweep_avg, 4),
@@ -191,6 +209,15 @@ def main():
         single = {"ms_per_lambda_single_launch": round(1e3 * single_s / B, 4),
                   "ms_per_lambda_batched": round(ms_per_step / B, 4),
                   "speedup_batched_vs_single": round((single_s / B) / (ms_per_step / 1e3 / B), 2)}
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)      # reads and writes copy_calib MiB each
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline and args.config in ("c4", "c2"):
