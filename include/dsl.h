@@ -110,6 +110,13 @@ typedef struct dsl_catalog_desc {
   const double* inj_ln_pdraw;
   int64_t n_draw;
   int32_t precision; /* DSL_PRECISION_FP64 or DSL_PRECISION_FP32 (FP32 weights, FP64 sums) */
+  /* Per-pixel random downsampling at upload (Sec. II C, "Memory Reduction
+   * Strategies"): when > 0, a pixel with more samples keeps exactly this many,
+   * those with the smallest keys splitmix64(seed + splitmix64(pixel << 32 | k))
+   * (k = position in the pixel; ties by k), in their original order.  N_s,i
+   * becomes the number of kept samples.  0 keeps every sample. */
+  int64_t max_samples_per_pixel;
+  uint64_t downsample_seed;
 } dsl_catalog_desc;
 
 typedef struct dsl_handle dsl_handle;
@@ -125,6 +132,11 @@ int dsl_create(const dsl_catalog_desc* desc, dsl_handle** out);
  *   "neff_min"   threshold of the pixel gate of Eq. (8), default 2 (ties pass)
  *   "gate_mode"  0 pixel gate (default), 1 also reject events whose N_eff < neff_min,
  *                2 no gate
+ *   "z_prior"    0 = each sample's redshift prior is its pixel's LOS table and the
+ *                selection term uses sky_z (dark sirens, Eq. 5; default); 1 = every
+ *                sample and injection uses the comoving-volume shape
+ *                dV_c/dz ∝ I(z)^2/E(z) of the point's Omega_m (spectral sirens,
+ *                the setting of the paper's O5 mock analysis); tables are ignored
  *   "max_batch"  largest B accepted (default 4096)
  *   "lambda_tile" Lambda per wavefront for the sweep (0 = automatic; 1, 4, 16, 64)
  *   "chunk"      target samples per work item (0 = automatic)
@@ -168,9 +180,10 @@ int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_log
                      double* d_neff_sel, uint32_t* d_flags, void* stream);
 
 /*
- * Choose the sweep configuration for batches of B points by timing the
- * candidates on the current device; the choice is cached in the handle and,
- * when cache_path is not NULL, in that JSON file (read first if it exists).
+ * Choose the sweep configuration (Lambda tile, chunk) for batches of B points
+ * by timing the candidates on the current device; the choice is cached in the
+ * handle and, when cache_path is not NULL, appended to that text file (one
+ * line per device/catalogue/B key; read first if it exists).
  */
 int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path);
 

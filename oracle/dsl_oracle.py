@@ -42,6 +42,11 @@ Readings where the paper is silent (each is listed in the design doc):
 * p_LOS,j: linear interpolation of the pixel's table on uniform nodes over
   [0, z_max], zero outside; samples with d_L > d_L(z_max) have zero weight;
 * ties at the N_eff threshold pass; a pixel with no non-zero weight fails.
+* spectral-siren mode (the paper's O5 mock analysis runs without a galaxy
+  catalogue, Sec. III B): the redshift prior of every sample and injection is
+  the comoving-volume shape dV_c/dz ∝ I(z)^2 / E(z) for the point's Omega_m
+  instead of a table; its (c/H0)^3 factor and normalisation are Lambda-only
+  and cancel between the events and alpha^N_det.
 
 Parity status: the functional forms of the mass and rate models are readings
 of cited, unprinted models, so agreement with the paper's own code is
@@ -295,18 +300,22 @@ def los_interp(tables, rows, z, z_max):
 # ---------------------------------------------------------------------------
 # Eq. (7): per-sample log weights
 # ---------------------------------------------------------------------------
-def log_weights(m1d, m2d, dl, ln_prior, tables, rows, z_max, L: Lam, margins=None):
+def log_weights(m1d, m2d, dl, ln_prior, tables, rows, z_max, L: Lam, margins=None, z_prior="los"):
     """ln w for detector-frame samples; -inf outside the model's support.
 
     ln_prior is ln pi_PE for posterior samples or ln p_draw for injections;
-    tables[rows] is each sample's redshift prior (pixel table, or sky table).
+    tables[rows] is each sample's redshift prior (pixel table, or sky table),
+    or, with z_prior="comoving", the comoving-volume shape I(z)^2 / E(z).
     """
     z, in_z = z_of_dl(dl, L.H0, L.Om, z_max)
     zs = torch.where(in_z, z, torch.full_like(z, 0.5 * z_max))
     opz = 1.0 + zs
     m1 = m1d / opz
     m2 = m2d / opz
-    los = los_interp(tables, rows, zs, z_max)
+    if z_prior == "comoving":
+        los = comoving_integral(zs, L.Om) ** 2 / E_of_z(zs, L.Om)
+    else:
+        los = los_interp(tables, rows, zs, z_max)
     los_ok = los > 0
     l_los = torch.log(torch.where(los_ok, los, torch.ones_like(los)))
     l_rate = log_psi(zs, L) - torch.log(opz)
@@ -348,6 +357,7 @@ def lse_all(x):
 class Options:
     neff_min: float = 2.0
     gate_mode: int = 0          # 0: per-pixel gate; 1: also per-event gate; 2: none
+    z_prior: str = "los"        # "los" (pixel tables) or "comoving" (spectral sirens)
 
 
 def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
@@ -363,7 +373,8 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
     rows = torch.from_numpy(cat.pix_los_row[pix].astype(np.int64))[torch.from_numpy(pix_of_samp)]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a[samp], dtype=np.float64))
     margins = [] if margin_out is not None else None
-    lw = log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), tables, rows, cat.z_max, L, margins)
+    lw = log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), tables, rows, cat.z_max, L, margins,
+                     z_prior=opt.z_prior)
     seg = torch.from_numpy(pix_of_samp)
     n_p = len(pix)
     lS1 = segment_lse(lw, seg, n_p)
@@ -402,20 +413,20 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
     return lnL, neff_ev
 
 
-def _selection_chunk(cat, sl, L: Lam, sky, margin_out=None):
+def _selection_chunk(cat, sl, L: Lam, sky, margin_out=None, z_prior="los"):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a[sl], dtype=np.float64))
     n = sl.stop - sl.start
     rows = torch.zeros(n, dtype=torch.int64)
     margins = [] if margin_out is not None else None
     lw = log_weights(t(cat.inj_m1d), t(cat.inj_m2d), t(cat.inj_dl), t(cat.inj_ln_pdraw),
-                     sky, rows, cat.z_max, L, margins)
+                     sky, rows, cat.z_max, L, margins, z_prior=z_prior)
     if margin_out is not None:
         margin_out.append(float(margins[0].min()) if n else math.inf)
     return lse_all(lw), lse_all(2.0 * lw)
 
 
 def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = False,
-            event_block: int = 64, inj_chunk: int = 1 << 20, margins: bool = False):
+            event_block: int = 64, inj_chunk: int = 1 << 20, margins: bool = False, z_prior: str = "los"):
     """Oracle log-likelihood of one hyperparameter point.
 
     Returns a dict with logL, logL_event[n_events], neff_event[n_events],
@@ -432,7 +443,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     if not lambda_is_valid(lam_np):
         out["flags"] = FLAG_INVALID_LAMBDA
         return out
-    opt = Options(neff_min=neff_min, gate_mode=gate_mode)
+    opt = Options(neff_min=neff_min, gate_mode=gate_mode, z_prior=z_prior)
     lam_t = torch.tensor(lam_np, dtype=DT, requires_grad=grad)
     L = Lam.of(lam_t)
     tables = torch.from_numpy(np.asarray(cat.los, dtype=np.float64))
@@ -460,7 +471,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         sl = slice(c0, min(cat.n_inj, c0 + inj_chunk))
         mo = [] if margins else None
         with torch.set_grad_enabled(grad):
-            l1, l2 = _selection_chunk(cat, sl, L, sky, mo)
+            l1, l2 = _selection_chunk(cat, sl, L, sky, mo, z_prior=z_prior)
             if grad and torch.isfinite(l1):
                 gc.append(torch.autograd.grad(l1, lam_t)[0])
             elif grad:
@@ -493,6 +504,44 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         out["sample_margin"] = samp_m
         out["inj_margin"] = inj_margin
     return out
+
+
+# ---------------------------------------------------------------------------
+# Per-pixel random downsampling (Sec. II C, "Memory Reduction Strategies")
+# ---------------------------------------------------------------------------
+_U64 = np.uint64
+
+
+def splitmix64(x):
+    """SplitMix64 output function (Steele, Lea & Flood 2014) on uint64 arrays."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(x, dtype=_U64) + _U64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U64(27))) * _U64(0x94D049BB133111EB)
+        return z ^ (z >> _U64(31))
+
+
+def downsample(cat, cap, seed):
+    """Keep at most `cap` samples per pixel: the ones with the smallest keys
+    splitmix64(seed + splitmix64(pixel << 32 | k)) (ties by k), in order."""
+    import dataclasses
+    keep = []
+    pso = [0]
+    for j in range(cat.n_pix):
+        s0, s1 = int(cat.pix_samp_off[j]), int(cat.pix_samp_off[j + 1])
+        n = s1 - s0
+        if n <= cap:
+            idx = np.arange(n)
+        else:
+            k = np.arange(n, dtype=_U64)
+            with np.errstate(over="ignore"):
+                key = splitmix64(_U64(seed) + splitmix64((_U64(j) << _U64(32)) | k))
+            idx = np.sort(np.lexsort((np.arange(n), key))[:cap])
+        keep.append(s0 + idx)
+        pso.append(pso[-1] + len(idx))
+    sel = np.concatenate(keep) if keep else np.zeros(0, np.int64)
+    return dataclasses.replace(cat, pix_samp_off=np.asarray(pso, np.int64), m1d=cat.m1d[sel], m2d=cat.m2d[sel],
+                               dl=cat.dl[sel], ln_pi=cat.ln_pi[sel])
 
 
 def loglike_batch(cat, lams, **kw):

@@ -39,6 +39,7 @@ class CatalogDesc(C.Structure):
         ("ln_pi", C.c_void_p),
         ("n_inj", C.c_int64), ("inj_m1d", C.c_void_p), ("inj_m2d", C.c_void_p), ("inj_dl", C.c_void_p),
         ("inj_ln_pdraw", C.c_void_p), ("n_draw", C.c_int64), ("precision", C.c_int32),
+        ("max_samples_per_pixel", C.c_int64), ("downsample_seed", C.c_uint64),
     ]
 
 
@@ -101,7 +102,8 @@ class DarkSirenLikelihood:
     """
 
     def __init__(self, catalog, precision: str = "fp32", neff_min: float = 2.0, gate_mode: int = 0,
-                 device: Optional[int] = None):
+                 device: Optional[int] = None, z_prior: str = "los", max_samples_per_pixel: int = 0,
+                 downsample_seed: int = 0):
         if not torch.cuda.is_available():
             raise DSLError("a GPU is required (the likelihood runs only in HIP kernels)")
         self.lib = load_library()
@@ -123,13 +125,15 @@ class DarkSirenLikelihood:
             n_z=keep["los"].shape[1], z_max=float(catalog.z_max), los=p(keep["los"]), sky_z=p(keep["sky"]),
             n_samp=len(keep["m1"]), m1d=p(keep["m1"]), m2d=p(keep["m2"]), dl=p(keep["dl"]), ln_pi=p(keep["lp"]),
             n_inj=len(keep["im1"]), inj_m1d=p(keep["im1"]), inj_m2d=p(keep["im2"]), inj_dl=p(keep["idl"]),
-            inj_ln_pdraw=p(keep["ilp"]), n_draw=int(catalog.n_draw), precision=prec)
+            inj_ln_pdraw=p(keep["ilp"]), n_draw=int(catalog.n_draw), precision=prec,
+            max_samples_per_pixel=int(max_samples_per_pixel), downsample_seed=int(downsample_seed))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(self.lib, self.lib.dsl_create(C.byref(d), C.byref(h)), "dsl_create")
         self.h = h
         self.set_option("neff_min", neff_min)
         self.set_option("gate_mode", gate_mode)
+        self.set_option("z_prior", {"los": 0, "comoving": 1}[z_prior])
 
     # -- options / info
     def set_option(self, key: str, value: float):

@@ -100,7 +100,7 @@ struct dsl_handle {
   int device = 0;
   int fp32 = 1;
   int n_cu = 256;
-  int64_t n_events = 0, n_pix = 0, n_samp = 0, n_inj = 0, n_draw = 0, n_rows = 0;
+  int64_t n_events = 0, n_pix = 0, n_samp = 0, n_inj = 0, n_draw = 0, n_rows = 0, n_samp_input = 0;
   int n_z = 0;
   double z_max = 0;
   std::vector<int64_t> epo, pso;   // host copies (work-list builder)
@@ -119,6 +119,7 @@ struct dsl_handle {
   int64_t chunk_opt = 0;
   int timing = 0;
   int graph = 1;
+  int z_prior = 0;
   int last_gl = 0;           // Lambda tile of the last call
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool have_timing = false;
@@ -184,6 +185,57 @@ int validate(const dsl_catalog_desc* d) {
   for (int i = 0; i < d->n_z; ++i)
     if (!std::isfinite(d->sky_z[i]) || d->sky_z[i] < 0) return fail(DSL_EINVAL, "sky_z must be finite and >= 0");
   return DSL_OK;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): the keys of the per-pixel downsampling.
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Downsampled {
+  dsl_catalog_desc desc;
+  std::vector<int64_t> pso;
+  std::vector<double> m1, m2, dl, lp;
+};
+
+// Keep at most max_samples_per_pixel samples per pixel: those with the
+// smallest keys (ties by position), in their original order.
+void downsample(const dsl_catalog_desc& d, Downsampled& o) {
+  const int64_t cap = d.max_samples_per_pixel;
+  o.desc = d;
+  o.pso.assign(1, 0);
+  std::vector<std::pair<uint64_t, int64_t>> keys;
+  std::vector<int64_t> keep;
+  for (int64_t j = 0; j < d.n_pix; ++j) {
+    const int64_t s0 = d.pix_samp_off[j], n = d.pix_samp_off[j + 1] - s0;
+    keep.clear();
+    if (n <= cap) {
+      for (int64_t k = 0; k < n; ++k) keep.push_back(k);
+    } else {
+      keys.resize(n);
+      for (int64_t k = 0; k < n; ++k)
+        keys[k] = {splitmix64(d.downsample_seed + splitmix64(((uint64_t)j << 32) | (uint64_t)k)), k};
+      std::nth_element(keys.begin(), keys.begin() + cap, keys.end());
+      for (int64_t k = 0; k < cap; ++k) keep.push_back(keys[k].second);
+      std::sort(keep.begin(), keep.end());
+    }
+    for (int64_t k : keep) {
+      o.m1.push_back(d.m1d[s0 + k]);
+      o.m2.push_back(d.m2d[s0 + k]);
+      o.dl.push_back(d.dl[s0 + k]);
+      o.lp.push_back(d.ln_pi[s0 + k]);
+    }
+    o.pso.push_back((int64_t)o.m1.size());
+  }
+  o.desc.pix_samp_off = o.pso.data();
+  o.desc.n_samp = (int64_t)o.m1.size();
+  o.desc.m1d = o.m1.data();
+  o.desc.m2d = o.m2.data();
+  o.desc.dl = o.dl.data();
+  o.desc.ln_pi = o.lp.data();
 }
 
 int upload(DevBuf& b, const void* src, size_t bytes) {
@@ -384,6 +436,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   a.B = B;
   a.neff_min = h->neff_min;
   a.gate_mode = h->gate_mode;
+  a.z_prior = h->z_prior;
   a.part = h->part.as<double>();
   const int n_tiles = (B + cfg.GL - 1) / cfg.GL;
   const int waves = cfg.waves;
@@ -392,6 +445,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   HIPCHK(launch_sweep(h->fp32, cfg.GL, grad, a, grid_x, 64 * waves, st));
   GateSplitArgs gs;
   gs.part = h->part.as<double>();
+  gs.n_items = h->n_items;
   gs.nf = grad ? NF_GRAD : NF_FWD;
   gs.B = B;
   gs.splits = h->splits.as<SplitPix>();
@@ -402,6 +456,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   if (timed) HIPCHK(hipEventRecord(h->ev[2], st));
   CombineArgs c;
   c.part = h->part.as<double>();
+  c.n_items = h->n_items;
   c.nf = grad ? NF_GRAD : NF_FWD;
   c.B = B;
   c.n_events = (int32_t)h->n_events;
@@ -483,11 +538,18 @@ const char* dsl_last_error(void) { return g_err.c_str(); }
 
 const char* dsl_version(void) { return "dsl 0.1 (gfx950)"; }
 
-int dsl_create(const dsl_catalog_desc* d, dsl_handle** out) {
+int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   if (!out) return fail(DSL_EINVAL, "out is NULL");
   *out = nullptr;
-  int rc = validate(d);
+  int rc = validate(d_in);
   if (rc) return rc;
+  if (d_in->max_samples_per_pixel < 0) return fail(DSL_EINVAL, "max_samples_per_pixel must be >= 0");
+  Downsampled ds;
+  const dsl_catalog_desc* d = d_in;
+  if (d_in->max_samples_per_pixel > 0) {
+    downsample(*d_in, ds);
+    d = &ds.desc;
+  }
   std::unique_ptr<dsl_handle> h(new (std::nothrow) dsl_handle());
   if (!h) return fail(DSL_ENOMEM, "host allocation");
   (void)hipGetLastError();
@@ -499,6 +561,7 @@ int dsl_create(const dsl_catalog_desc* d, dsl_handle** out) {
   h->n_events = d->n_events;
   h->n_pix = d->n_pix;
   h->n_samp = d->n_samp;
+  h->n_samp_input = d_in->n_samp;
   h->n_inj = d->n_inj;
   h->n_draw = d->n_draw;
   h->n_rows = d->n_los_rows;
@@ -549,6 +612,9 @@ int dsl_set_option(dsl_handle* h, const char* key, double v) {
   } else if (k == "chunk") {
     if (v < 0 || v > (1 << 24)) return fail(DSL_EINVAL, "chunk out of range");
     h->chunk_opt = (int64_t)v;
+  } else if (k == "z_prior") {
+    if (v != 0 && v != 1) return fail(DSL_EINVAL, "z_prior must be 0 (LOS tables) or 1 (comoving volume)");
+    h->z_prior = (int)v;
   } else if (k == "timing") {
     h->timing = v != 0;
   } else if (k == "graph") {
@@ -569,6 +635,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   if (k == "n_events") *v = (double)h->n_events;
   else if (k == "n_pix") *v = (double)h->n_pix;
   else if (k == "n_samp") *v = (double)h->n_samp;
+  else if (k == "n_samp_input") *v = (double)h->n_samp_input;
   else if (k == "n_inj") *v = (double)h->n_inj;
   else if (k == "n_draw") *v = (double)h->n_draw;
   else if (k == "n_z") *v = (double)h->n_z;
@@ -577,6 +644,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "precision") *v = h->fp32 ? DSL_PRECISION_FP32 : DSL_PRECISION_FP64;
   else if (k == "neff_min") *v = h->neff_min;
   else if (k == "gate_mode") *v = h->gate_mode;
+  else if (k == "z_prior") *v = h->z_prior;
   else if (k == "max_batch") *v = h->max_batch;
   else if (k == "lambda_tile") *v = h->lambda_tile;
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);

@@ -111,11 +111,13 @@ struct SweepArgs {
   int32_t B;
   double neff_min;
   int32_t gate_mode;
-  double* part;              // [n_items][NF][B]
+  int32_t z_prior;           // 0: LOS tables; 1: comoving volume (spectral sirens)
+  double* part;              // [B][n_items][NF]
 };
 
 struct GateSplitArgs {
-  double* part;
+  double* part;              // [B][n_items][nf]
+  int32_t n_items;
   int32_t nf;
   int32_t B;
   const SplitPix* splits;
@@ -125,7 +127,8 @@ struct GateSplitArgs {
 };
 
 struct CombineArgs {
-  const double* part;
+  const double* part;        // [B][n_items][nf]
+  int32_t n_items;
   int32_t nf;                // NF_FWD or NF_GRAD
   int32_t B;
   int32_t n_events;

@@ -481,18 +481,26 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T lm1 = sp.lm1d - L, lm2 = sp.lm2d - L;
   (void)lm2;
   ok = ok && (m1 <= c.mmax) && (m2 > c.mmin) && (m2 <= m1);
-  // p_LOS(z): linear interpolation of the pixel's table (Eq. 5).
-  const T xz = z * inv_dz;
-  int kz = (int)xz;
-  kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
-  const T fz = xz - (T)kz;
-  const T l0 = (T)los[kz], l1 = (T)los[kz + 1];
-  const T losv = l0 + fz * (l1 - l0);
-  ok = ok && (losv > (T)0);
   // Jacobian: |J| = (1+z)^2 (c/H0) D'(z), D' = I + (1+z)/E, I = u/(1+z).
   const T E2 = c.Om * opz * opz * opz + c.OL;
   const T rE = M::rsqrt(E2);
-  const T Dp = u * r + opz * rE;
+  const T I = u * r;
+  const T Dp = I + opz * rE;
+  // Redshift prior: the pixel's table, linearly interpolated (Eq. 5), or, for
+  // spectral sirens (los == nullptr), the comoving-volume shape I^2 / E.
+  T l0 = 0, l1 = 0, losv;
+  if (los) {
+    const T xz = z * inv_dz;
+    int kz = (int)xz;
+    kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
+    const T fz = xz - (T)kz;
+    l0 = (T)los[kz];
+    l1 = (T)los[kz + 1];
+    losv = l0 + fz * (l1 - l0);
+  } else {
+    losv = I * I * rE;
+  }
+  ok = ok && (losv > (T)0);
   // Madau-Dickinson: psi/(1+z) = (1+z)^(gamma-1) / (1 + 2^eX).
   const T eX = c.gk * (L - c.Lp);
   const T aX = M::exp2(-fabs(eX));
@@ -578,14 +586,14 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       dlnS2_dm = omS * c.dm * (inv_mp * inv_mp + inv_mq * inv_mq);
       dlnS2_ddm = -omS * (inv_mp + mp2 * inv_mq * inv_mq);
     }
-    // d ln w / dz at fixed Lambda (LOS slope, rate, Jacobian, mass chain)
-    const T dlos = (l1 - l0) * inv_dz;
+    // d ln w / dz at fixed Lambda (prior slope, rate, Jacobian, mass chain)
+    const T dlnlos = los ? (l1 - l0) * inv_dz * rlos
+                         : (T)2 * rE * (I * rE * rlos) - (T)1.5 * c.Om * opz * opz * rE * rE;
     const T Dpp = rE * ((T)2 - (T)1.5 * c.Om * opz * opz * opz * rE * rE);
-    T Gz = dlos * rlos + (c.gm3 - sig * c.gk) * r - Dpp * rDp;
+    T Gz = dlnlos + (c.gm3 - sig * c.gk) * r - Dpp * rDp;
     Gz -= r * (m1dmix - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
     // dz/dH0 = (d_L/c)/D', dz/dOm = -(1+z) dI/dOm / D'
     const T dz_dH0 = sp.dlc * rDp;
-    const T I = u * r;
     T dI_dOm;
     if (c.om_case == 0) {
       const T K = (opz * rE - (T)1 + (T)0.5 * I) * c.k23;
@@ -625,6 +633,9 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     // the per-point coefficients C are applied once per point in combine_kernel.
     g[0] = Gz * dz_dH0;
     g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
+    if (!los) {   // explicit Omega_m dependence of ln(I^2 / E) at fixed z
+      g[1] += (T)2 * dI_dOm * (I * rE * rlos) - (T)0.5 * (opz * opz * opz - (T)1) * rE * rE;
+    }
     g[2] = fP;
     g[3] = fP * lnm1;
     g[4] = lnq - drho_b * rrho;
@@ -825,7 +836,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
     int npass = 0;
     if (w.event >= 0 && w.pix1 == w.pix0) {
       // part of a large pixel: ungated sums, gated after the sweep (gate_split_kernel)
-      const float* __restrict__ tab = a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
+      const float* __restrict__ tab = a.z_prior ? nullptr : a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
       PixAcc<GRAD, T> pix;
       pix.zero();
       sweep_run<T, GL, GRAD>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
@@ -835,7 +846,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
     } else if (w.event >= 0) {
       for (int p = w.pix0; p < w.pix1; ++p) {
         const int64_t s0 = a.pix_off[p], s1 = a.pix_off[p + 1];
-        const float* __restrict__ tab = a.los + (size_t)a.pix_row[p] * a.n_z;
+        const float* __restrict__ tab = a.z_prior ? nullptr : a.los + (size_t)a.pix_row[p] * a.n_z;
         PixAcc<GRAD, T> pix;
         pix.zero();
         sweep_run<T, GL, GRAD>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
@@ -856,21 +867,23 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         PixAcc<GRAD, T> pix;
         pix.zero();
         const int64_t v1 = v0 + VP < w.s1 ? v0 + VP : w.s1;
-        sweep_run<T, GL, GRAD>(inj, v0, v1, sg, live, c, tv, lam, a.sky, a.n_z, inv_dz, pix, g);
+        sweep_run<T, GL, GRAD>(inj, v0, v1, sg, live, c, tv, lam, a.z_prior ? nullptr : a.sky, a.n_z, inv_dz,
+                               pix, g);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         chunk.merge(pix);
       }
     }
     if (sg == 0 && active) {
-      double* out = a.part + (size_t)w.slot * NF * a.B + b;
+      // partial sums laid out [point][item][field]: one lane writes its fields contiguously
+      double* out = a.part + ((size_t)b * a.n_items + w.slot) * NF;
       out[0] = (double)chunk.R;
-      out[(size_t)a.B] = chunk.S1;
-      out[(size_t)2 * a.B] = chunk.S2;
-      out[(size_t)3 * a.B] = (double)npass;
+      out[1] = chunk.S1;
+      out[2] = chunk.S2;
+      out[3] = (double)npass;
       if constexpr (GRAD) {
 #pragma unroll
-        for (int p = 0; p < 16; ++p) out[(size_t)(4 + p) * a.B] = chunk.G[p];
+        for (int p = 0; p < 16; ++p) out[4 + p] = chunk.G[p];
       }
     }
   }
@@ -885,7 +898,7 @@ __global__ __launch_bounds__(256) void gate_split_kernel(GateSplitArgs a) {
   if (i >= (int64_t)a.n_split * a.B) return;
   const int sp = (int)(i / a.B), b = (int)(i % a.B);
   const SplitPix s = a.splits[sp];
-  auto at = [&](int slot, int f) -> double& { return a.part[((size_t)slot * a.nf + f) * a.B + b]; };
+  auto at = [&](int slot, int f) -> double& { return a.part[((size_t)b * a.n_items + slot) * a.nf + f]; };
   double R = -1e300, S1 = 0, S2 = 0;
   double G[16];
   for (int p = 0; p < 16; ++p) G[p] = 0;
@@ -945,7 +958,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   const int B = a.B;
   const double ln2 = LN2;
   const double* P = a.part;
-  auto at = [&](int slot, int f) { return P[((size_t)slot * a.nf + f) * B + b]; };
+  auto at = [&](int slot, int f) { return P[((size_t)b * a.n_items + slot) * a.nf + f]; };
   const bool valid = a.valid[b] != 0;
   __shared__ double red[256];
   __shared__ double redg[GRAD ? 16 : 1][256];

@@ -35,6 +35,7 @@ def test_header_layout_matches_binding():
     binding, _ = _lib()
     src = open(HEADER).read()
     body = src[src.index("typedef struct dsl_catalog_desc"):src.index("} dsl_catalog_desc;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     c_fields = re.findall(r"\b(\w+);", body)
     assert [f for f, _ in binding.CatalogDesc._fields_] == c_fields
 

@@ -89,3 +89,47 @@ def test_gradient_matches_oracle(env, precision):
         assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32)
         check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
     lik.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_spectral_sirens(env, precision):
+    """Comoving-volume redshift prior (no galaxy catalogue): value and gradient."""
+    torch, O, cat = env["torch"], env["O"], env["cat"]
+    log(f"[spectral {precision}]")
+    lik = env["binding"].DarkSirenLikelihood(cat, precision=precision, z_prior="comoving")
+    lam = _lam(env, 5, seed=13)
+    r = lik.loglike_grad(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    tol = TOL_LOGL_FP32 if precision == "fp32" else TOL_LOGL_FP64
+    for b in range(len(lam)):
+        ref = O.loglike(cat, lam[b], grad=True, margins=True, z_prior="comoving")
+        assert int(r["flags"][b]) == ref["flags"]
+        if ref["flags"]:
+            continue
+        assert rel_close(float(r["logL"][b]), ref["logL"], tol), (b, float(r["logL"][b]), ref["logL"])
+        check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, tol)
+        check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
+    lik.close()
+
+
+def test_downsampled_catalogue(env):
+    """At most 60 samples per pixel kept at upload (SplitMix64 keys) = the
+    oracle on the catalogue downsampled by the same rule."""
+    torch, O, cat = env["torch"], env["O"], env["cat"]
+    log("[downsampled 60/pixel]")
+    lik = env["binding"].DarkSirenLikelihood(cat, max_samples_per_pixel=60, downsample_seed=11)
+    ds = O.downsample(cat, 60, seed=11)
+    assert int(lik.info("n_samp")) == ds.n_samp < cat.n_samp
+    assert int(lik.info("n_samp_input")) == cat.n_samp
+    lam = _lam(env, 4, seed=17)
+    r = lik.loglike_grad(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    for b in range(len(lam)):
+        ref = O.loglike(ds, lam[b], grad=True, margins=True)
+        assert int(r["flags"][b]) == ref["flags"]
+        if ref["flags"]:
+            continue
+        assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32)
+        check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, TOL_LOGL_FP32)
+        check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
+    lik.close()

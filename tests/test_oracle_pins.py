@@ -437,3 +437,59 @@ def test_gradient_vs_central_differences():
         lm[p] -= h
         fd = (O.loglike(cat, lp)["logL"] - O.loglike(cat, lm)["logL"]) / (2 * h)
         assert abs(fd - g[p]) <= 2e-6 * gn + 1e-5 * abs(g[p]), (synth.LAMBDA_NAMES[p], fd, g[p])
+
+
+# ---------------------------------------------------------------- spectral sirens
+def test_gaussian_toy_spectral():
+    """Comoving-volume redshift prior, Omega_m = 0: I(z) = z, E = 1, so the prior
+    is z^2; each toy event likelihood gains z_i^2 and alpha = (1/2) int z^2/(1+z) dz
+    = (1/2) ln 3 over [0, 2]."""
+    H0, mu, sigma = 70.0, 30.0, 3.0
+    cat = F.make_toy_catalog(TOY_EVENTS, H0, mu, sigma)
+    r = O.loglike(cat, F.toy_lambda(H0, mu, sigma), z_prior="comoving")
+    n_s = cat.samples_per_event()
+    for i, (x, s, d) in enumerate(TOY_EVENTS):
+        z = F.z_closed_om0(d, H0)
+        truth = F.toy_event_truth(x, s, d, H0, mu, sigma) * z * z
+        assert abs(r["logL_event"][i] + math.log(n_s[i]) - math.log(truth)) < 1e-11
+    assert abs(r["ln_alpha"] - math.log(0.5 * math.log(3.0))) < 1e-10
+
+
+def test_comoving_prior_einstein_de_sitter():
+    """Omega_m = 1: I = 2 (1 - (1+z)^-1/2), E = (1+z)^3/2 (closed forms)."""
+    z = np.array([0.1, 0.5, 1.3])
+    L = _L(Om=1.0)
+    I = O.comoving_integral(T(z), L.Om).numpy()
+    E = O.E_of_z(T(z), L.Om).numpy()
+    ref = (2 * (1 - (1 + z) ** -0.5)) ** 2 / (1 + z) ** 1.5
+    np.testing.assert_allclose(I ** 2 / E, ref, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- downsampling
+def test_splitmix64_reference_values():
+    """Published SplitMix64 test vector: seed 1234567 -> 6457827717110365317,
+    3203168211198807973 (the generator's state advances by the golden gamma)."""
+    g = 0x9E3779B97F4A7C15
+    s1 = (1234567 + 0 * g) % 2 ** 64
+    s2 = (1234567 + 1 * g) % 2 ** 64
+    out = O.splitmix64(np.array([s1, s2], dtype=np.uint64))
+    assert int(out[0]) == 6457827717110365317
+    assert int(out[1]) == 3203168211198807973
+
+
+def test_downsample_keeps_cap_per_pixel():
+    cat = synth.make_catalog("c1", n_events=2, n_inj=100)
+    ds = O.downsample(cat, 50, seed=7)
+    counts = np.diff(ds.pix_samp_off)
+    np.testing.assert_array_equal(counts, np.minimum(np.diff(cat.pix_samp_off), 50))
+    # kept samples are a subset of each pixel, in their original order
+    for j in range(cat.n_pix):
+        a, b = cat.pix_samp_off[j], cat.pix_samp_off[j + 1]
+        c, d = ds.pix_samp_off[j], ds.pix_samp_off[j + 1]
+        src = cat.dl[a:b]
+        got = ds.dl[c:d]
+        pos = [int(np.flatnonzero(src == v)[0]) for v in got]
+        assert pos == sorted(pos)
+    # a different seed keeps a different subset
+    ds2 = O.downsample(cat, 50, seed=8)
+    assert not np.array_equal(ds.dl, ds2.dl)
