@@ -48,6 +48,21 @@ Readings where the paper is silent (each is listed in the design doc):
   instead of a table; its (c/H0)^3 factor and normalisation are Lambda-only
   and cancel between the events and alpha^N_det.
 
+The paper's own numerator (loglike_kde; Eq. 6 inside Eq. 5, bandwidth rules of
+Appendix D) replaces the per-sample sum of a pixel by the integral over a
+redshift grid of a weighted Gaussian KDE of the samples' redshifts times the
+pixel's redshift prior and psi(z)/(1+z).  Readings: the Eq. (7) weights of this
+form carry the mass model, the Jacobian and the PE prior (the redshift prior
+and the rate act on the grid, as the paper's per-component timing lists them);
+the bandwidths use the unweighted in-support redshifts of the pixel (the
+printed rules are unweighted), n their number, the sample standard deviation
+with n - 1, quantiles by linear interpolation, the biweight scale as the
+square root of the printed midvariance inside Scott's form; the grid is
+KDE_GRID uniform nodes from max(0, min z - 5h) to min(z_max, max z + 5h)
+integrated by the trapezoid rule; a zero bandwidth (one sample, equal
+redshifts, zero MAD) takes the point-mass limit; Eq. (8) gates with the same
+weights.
+
 Parity status: the functional forms of the mass and rate models are readings
 of cited, unprinted models, so agreement with the paper's own code is
 "parity unpinned"; every function below is pinned by the tests in
@@ -503,6 +518,255 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         out["gate_margin"] = gate_m
         out["sample_margin"] = samp_m
         out["inj_margin"] = inj_margin
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's KDE numerator (Eq. 6 inside Eq. 5; bandwidths of Appendix D)
+# ---------------------------------------------------------------------------
+KDE_GRID = 256     # fiducial resolution of the redshift grid (Sec. III C)
+KDE_TAU = 5.0      # the grid reaches this many bandwidths beyond the outermost sample
+
+
+def kde_log_weights(m1d, m2d, dl, ln_prior, z_max, L: Lam):
+    """Eq. (7) weights of the KDE form: the mass population over the PE prior
+    expressed in (m1, m2, z), i.e. divided by the Jacobian (1+z)^2 dd_L/dz.
+    The redshift prior and the rate enter on the grid.  Returns (z, inside, ln w)
+    with ln w = -inf outside the mass support."""
+    z, in_z = z_of_dl(dl, L.H0, L.Om, z_max)
+    zs = torch.where(in_z, z, torch.full_like(z, 0.5 * z_max))
+    opz = 1.0 + zs
+    m1 = m1d / opz
+    m2 = m2d / opz
+    l_mass = log_p1(m1, L) + log_p2(m2, m1, L)
+    l_jac = 2.0 * torch.log(opz) + torch.log(ddl_dz(zs, L.H0, L.Om))
+    lw = l_mass - l_jac - ln_prior
+    ok = in_z & torch.isfinite(l_mass)
+    return zs, in_z, torch.where(ok, lw, torch.full_like(lw, -math.inf))
+
+
+def _sorted(z):
+    return torch.sort(z).values
+
+
+def median(z):
+    """Median with the average of the two middle values for even n."""
+    s = _sorted(z)
+    n = s.numel()
+    return 0.5 * (s[(n - 1) // 2] + s[n // 2])
+
+
+def quantile_linear(z, p):
+    """Quantile at probability p by linear interpolation between order
+    statistics at position p (n - 1)."""
+    s = _sorted(z)
+    n = s.numel()
+    pos = p * (n - 1)
+    a = min(int(math.floor(pos)), n - 1)
+    b = min(a + 1, n - 1)
+    f = pos - a
+    return s[a] + f * (s[b] - s[a])
+
+
+def sample_std(z):
+    """Sample standard deviation (n - 1 in the denominator), computed about
+    the first value so that equal values give exactly 0."""
+    d = z - z[0].detach()
+    d = d - torch.mean(d)
+    return torch.sqrt(torch.sum(d * d) / (z.numel() - 1))
+
+
+def bw_scott(z):
+    """Appendix D, Scott's rule: h = 1.06 sigma n^(-1/5), sigma the sample
+    standard deviation."""
+    n = z.numel()
+    if n < 2:
+        return torch.zeros((), dtype=DT)
+    return 1.06 * sample_std(z) * n ** -0.2
+
+
+def bw_silverman(z):
+    """Appendix D, Silverman's rule: h = 0.9 min(sigma, IQR/1.34) n^(-1/5)."""
+    n = z.numel()
+    if n < 2:
+        return torch.zeros((), dtype=DT)
+    iqr = quantile_linear(z, 0.75) - quantile_linear(z, 0.25)
+    return 0.9 * torch.minimum(sample_std(z), iqr / 1.34) * n ** -0.2
+
+
+def biweight_midvariance(z):
+    """Appendix D, biweight midvariance about the median Q with u scaled by
+    9 MAD; 0 when the MAD is 0."""
+    n = z.numel()
+    if n < 2:
+        return torch.zeros((), dtype=DT)
+    Q = median(z)
+    mad = median(torch.abs(z - Q))
+    if float(mad) == 0.0:
+        return torch.zeros((), dtype=DT)
+    u = (z - Q) / (9.0 * mad)
+    inside = torch.abs(u.detach()) < 1.0
+    d = torch.where(inside, z - Q, torch.zeros_like(z))
+    uu = torch.where(inside, u * u, torch.zeros_like(u))
+    num = n * torch.sum(d * d * (1.0 - uu) ** 4)
+    den = torch.sum(torch.where(inside, (1.0 - uu) * (1.0 - 5.0 * uu), torch.zeros_like(uu))) ** 2
+    return num / den
+
+
+def bw_biweight(z):
+    """Bandwidth from the biweight scale: Scott's form with sigma replaced by
+    the square root of the biweight midvariance (Appendix D prints the
+    midvariance itself, a squared scale)."""
+    n = z.numel()
+    v = biweight_midvariance(z)
+    if float(v) <= 0.0:
+        return torch.zeros((), dtype=DT)
+    return 1.06 * torch.sqrt(v) * n ** -0.2
+
+
+BANDWIDTHS = {"scott": bw_scott, "silverman": bw_silverman, "biweight": bw_biweight}
+
+
+def kde_grid(z, h, z_max, n_grid=KDE_GRID, tau=KDE_TAU):
+    """n_grid uniform nodes from max(0, min z - tau h) to min(z_max, max z + tau h)."""
+    a = torch.clamp(torch.min(z) - tau * h, min=0.0)
+    b = torch.clamp(torch.max(z) + tau * h, max=z_max)
+    g = torch.arange(n_grid, dtype=DT) / (n_grid - 1)
+    return a + g * (b - a)
+
+
+def kde_pixel_integral(z, w, h, grid, v):
+    """Trapezoid rule over the grid of f(z_g) v_g with the weighted Gaussian
+    KDE f(z) = sum_k w_k N(z; z_k, h^2) (Eq. 6)."""
+    x = (grid[:, None] - z[None, :]) / h
+    K = torch.exp(-0.5 * x * x) / (h * math.sqrt(2.0 * math.pi))
+    y = (K @ w) * v
+    dz = grid[1] - grid[0]
+    return dz * (torch.sum(y) - 0.5 * (y[0] + y[-1]))
+
+
+def _pixel_kde_term(z, lw, h, table, z_max, L: Lam, n_grid):
+    """ln of the pixel's integral of KDE x redshift prior x psi(z)/(1+z)."""
+    mx = torch.max(lw.detach())
+    w = torch.exp(lw - mx)
+    if float(h) > 0.0:
+        grid = kde_grid(z, h, z_max, n_grid)
+        v = los_interp(table, torch.zeros(n_grid, dtype=torch.int64), grid, z_max) * \
+            torch.exp(log_psi(grid, L) - torch.log1p(grid))
+        T = kde_pixel_integral(z, w, h, grid, v)
+    else:   # zero bandwidth: the kernel is a point mass at each sample
+        v = los_interp(table, torch.zeros(z.numel(), dtype=torch.int64), z, z_max) * \
+            torch.exp(log_psi(z, L) - torch.log1p(z))
+        T = torch.sum(w * v)
+    if float(T) <= 0.0:
+        return torch.tensor(-math.inf, dtype=DT)
+    return torch.log(T) + mx
+
+
+def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff_min: float = 2.0,
+                gate_mode: int = 0, grad: bool = False, margins: bool = False):
+    """Oracle log-likelihood with the paper's KDE numerator.
+
+    For every pixel j of event i: the in-support samples (d_L <= d_L(z_max))
+    with their Eq. (7) weights w_k (kde_log_weights) form the KDE of Eq. (6)
+    with the pixel's bandwidth h_j (Appendix D, from the samples' redshifts);
+    T_j = integral over the grid of KDE(z) p_LOS,j(z) psi(z)/(1+z) (trapezoid
+    rule on kde_grid); the pixel passes Eq. (8) on the same weights; and
+    L_i = (1/N_s,i) sum_pass T_j.  The selection term is the Monte Carlo sum
+    over injections, exactly as in loglike.  Pure-Python loop over pixels.
+    """
+    lam_np = np.asarray(lam, dtype=np.float64).reshape(16)
+    nE = cat.n_events
+    out = dict(logL=-math.inf, logL_event=np.full(nE, -math.inf), neff_event=np.zeros(nE),
+               neff_sel=0.0, flags=0, grad=np.zeros(16))
+    if not lambda_is_valid(lam_np):
+        out["flags"] = FLAG_INVALID_LAMBDA
+        return out
+    bw = BANDWIDTHS[bandwidth]
+    lam_t = torch.tensor(lam_np, dtype=DT, requires_grad=grad)
+    L = Lam.of(lam_t)
+    tables = torch.from_numpy(np.asarray(cat.los, dtype=np.float64))
+    sky = torch.from_numpy(np.asarray(cat.sky_z, dtype=np.float64)).reshape(1, -1)
+    log_nmin = math.log(neff_min) if neff_min > 0 else -math.inf
+    lnL_ev = np.empty(nE)
+    neff_ev = np.empty(nE)
+    gate_m = np.full(nE, math.inf)
+    samp_m = np.full(nE, math.inf)
+    g_ev = torch.zeros(16, dtype=DT)
+    umax = (1.0 + cat.z_max) * float(comoving_integral(torch.tensor(cat.z_max, dtype=DT), torch.tensor(lam_np[1])))
+    with torch.set_grad_enabled(grad):
+        for i in range(nE):
+            lT, lS1, lS2, n_s = [], [], [], 0
+            for j in range(int(cat.event_pix_off[i]), int(cat.event_pix_off[i + 1])):
+                s0, s1 = int(cat.pix_samp_off[j]), int(cat.pix_samp_off[j + 1])
+                n_s += s1 - s0
+                if s1 == s0:
+                    continue
+                t = lambda a: torch.from_numpy(np.ascontiguousarray(a[s0:s1], dtype=np.float64))
+                z, inside, lw = kde_log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), cat.z_max, L)
+                if margins:
+                    u = t(cat.dl) * lam_np[0] / C_KMS
+                    samp_m[i] = min(samp_m[i], float(torch.min(torch.abs(u / umax - 1.0))))
+                z, lw = z[inside], lw[inside]
+                if z.numel() == 0:
+                    continue
+                l1 = lse_all(lw)
+                l2 = lse_all(2.0 * lw)
+                lneff = float(2.0 * l1 - l2) if math.isfinite(float(l1)) else -math.inf
+                if margins and math.isfinite(lneff):
+                    gate_m[i] = min(gate_m[i], abs(lneff - log_nmin))
+                if not math.isfinite(float(l1)) or (gate_mode != 2 and lneff < log_nmin):
+                    continue
+                h = bw(z)
+                lT.append(_pixel_kde_term(z, lw, h, tables[int(cat.pix_los_row[j])].reshape(1, -1), cat.z_max,
+                                          L, n_grid))
+                lS1.append(l1)
+                lS2.append(l2)
+            if lT:
+                lE = torch.logsumexp(torch.stack(lT), 0)
+                e1 = float(torch.logsumexp(torch.stack(lS1), 0))
+                e2 = float(torch.logsumexp(torch.stack(lS2), 0))
+                neff = math.exp(2 * e1 - e2)
+            else:
+                lE = torch.tensor(-math.inf, dtype=DT)
+                neff = 0.0
+            lnL = lE - math.log(max(n_s, 1))
+            if gate_mode == 1 and neff < neff_min:
+                lnL = torch.tensor(-math.inf, dtype=DT)
+            lnL_ev[i] = float(lnL)
+            neff_ev[i] = neff
+            if grad and math.isfinite(float(lnL)):
+                g_ev += torch.autograd.grad(lnL, lam_t, allow_unused=True)[0]
+    lc1, lc2, gc = [], [], []
+    for c0 in range(0, cat.n_inj, 1 << 20):
+        sl = slice(c0, min(cat.n_inj, c0 + (1 << 20)))
+        with torch.set_grad_enabled(grad):
+            l1, l2 = _selection_chunk(cat, sl, L, sky)
+            if grad:
+                gc.append(torch.autograd.grad(l1, lam_t)[0] if torch.isfinite(l1) else torch.zeros(16, dtype=DT))
+        lc1.append(float(l1.detach()))
+        lc2.append(float(l2.detach()))
+    l1 = torch.logsumexp(torch.tensor(lc1, dtype=DT), 0)
+    l2 = torch.logsumexp(torch.tensor(lc2, dtype=DT), 0)
+    ln_alpha = float(l1) - math.log(cat.n_draw)
+    neff_sel = math.exp(2 * float(l1) - float(l2)) if math.isfinite(float(l1)) else 0.0
+    flags = 0
+    if not np.all(np.isfinite(lnL_ev)):
+        flags |= FLAG_EVENT_NO_PIXEL
+    if not math.isfinite(ln_alpha):
+        flags |= FLAG_ALPHA_ZERO
+    total = float(np.sum(lnL_ev)) - nE * ln_alpha if flags == 0 else -math.inf
+    if flags == 0 and not math.isfinite(total):
+        flags |= FLAG_NONFINITE
+        total = -math.inf
+    out.update(logL=total, logL_event=lnL_ev, neff_event=neff_ev, neff_sel=neff_sel, flags=flags,
+               ln_alpha=ln_alpha)
+    if grad and flags == 0:
+        wts = torch.softmax(torch.tensor(lc1, dtype=DT), 0)
+        out["grad"] = (g_ev - nE * sum(w * g for w, g in zip(wts, gc))).numpy()
+    if margins:
+        out["gate_margin"] = gate_m
+        out["sample_margin"] = samp_m
     return out
 
 
