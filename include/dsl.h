@@ -137,6 +137,20 @@ int dsl_create(const dsl_catalog_desc* desc, dsl_handle** out);
  *                sample and injection uses the comoving-volume shape
  *                dV_c/dz ∝ I(z)^2/E(z) of the point's Omega_m (spectral sirens,
  *                the setting of the paper's O5 mock analysis); tables are ignored
+ *   "numerator"  0 = each pixel contributes the sum of its samples' weights (default);
+ *                1 = the paper's KDE form (Eq. 6): the pixel's weighted Gaussian KDE
+ *                in redshift, weights of Eq. (7) without prior and rate, times the
+ *                pixel's LOS table and psi(z)/(1+z), integrated by the trapezoid rule
+ *                on "kde_grid" uniform nodes from max(0, min z - 5h) to
+ *                min(z_max, max z + 5h) over the pixel's in-support samples; the gate
+ *                of Eq. (8) uses the same weights.  Value only (dsl_loglike_grad
+ *                returns DSL_EINVAL) and only with z_prior 0
+ *   "kde_bandwidth" 0 Scott 1.06 s n^-1/5 (default), 1 Silverman
+ *                0.9 min(s, IQR/1.34) n^-1/5, 2 biweight 1.06 sqrt(midvariance) n^-1/5
+ *                (Appendix D), over the pixel's in-support redshifts (unweighted, s with
+ *                n - 1, linear quantiles); h = 0 (one sample, equal values, zero MAD)
+ *                makes each sample a point mass
+ *   "kde_grid"   grid nodes of the KDE numerator, 2 ... 1024 (default 256, Sec. III C)
  *   "max_batch"  largest B accepted (default 4096)
  *   "lambda_tile" Lambda per wavefront for the sweep (0 = automatic; 1, 4, 16, 64)
  *   "chunk"      target samples per work item (0 = automatic)

@@ -99,11 +99,15 @@ class DarkSirenLikelihood:
 
     catalog: a paper_2605_23538_amd.synth.Catalog (or any object with the same
     CSR arrays).  precision: "fp32" (FP32 weights, FP64 sums) or "fp64".
+    numerator: "mc" (per-sample sum over each pixel) or "kde" (the weighted
+    Gaussian KDE in redshift of Eq. 6 integrated against the pixel's prior on
+    a kde_grid-node grid, bandwidth rule kde_bandwidth; value only).
     """
 
     def __init__(self, catalog, precision: str = "fp32", neff_min: float = 2.0, gate_mode: int = 0,
                  device: Optional[int] = None, z_prior: str = "los", max_samples_per_pixel: int = 0,
-                 downsample_seed: int = 0):
+                 downsample_seed: int = 0, numerator: str = "mc", kde_bandwidth: str = "scott",
+                 kde_grid: int = 256):
         if not torch.cuda.is_available():
             raise DSLError("a GPU is required (the likelihood runs only in HIP kernels)")
         self.lib = load_library()
@@ -134,6 +138,9 @@ class DarkSirenLikelihood:
         self.set_option("neff_min", neff_min)
         self.set_option("gate_mode", gate_mode)
         self.set_option("z_prior", {"los": 0, "comoving": 1}[z_prior])
+        self.set_option("numerator", {"mc": 0, "kde": 1}[numerator])
+        self.set_option("kde_bandwidth", {"scott": 0, "silverman": 1, "biweight": 2}[kde_bandwidth])
+        self.set_option("kde_grid", kde_grid)
 
     # -- options / info
     def set_option(self, key: str, value: float):

@@ -28,6 +28,7 @@ hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* 
 hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
+hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st);
 hipError_t init_kernel_attrs();
 }  // namespace dsl
 
@@ -105,12 +106,13 @@ struct dsl_handle {
   double z_max = 0;
   std::vector<int64_t> epo, pso;   // host copies (work-list builder)
   DevBuf samp, inj, pix_off, pix_row, los, sky, ln_ns;
+  DevBuf ev_pix_off, perm;         // KDE numerator: event -> pixels, per-pixel d_L order
   // work list (for the current chunk size)
   int64_t built_chunk = -1;
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -120,6 +122,9 @@ struct dsl_handle {
   int timing = 0;
   int graph = 1;
   int z_prior = 0;
+  int numerator = 0;         // 0 per-sample Monte Carlo sum, 1 the KDE of Eq. (6)
+  int kde_bandwidth = 0;     // 0 Scott, 1 Silverman, 2 biweight (Appendix D)
+  int kde_grid = 256;
   int last_gl = 0;           // Lambda tile of the last call
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool have_timing = false;
@@ -397,6 +402,9 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
   const size_t nf = grad ? NF_GRAD : NF_FWD;
   if ((e = h->part.ensure(sizeof(double) * nf * (size_t)B * std::max(h->n_items, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (partials)");
+  if (h->numerator == 1 &&
+      (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_pix, 1))) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
   return DSL_OK;
 }
 
@@ -437,6 +445,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   a.neff_min = h->neff_min;
   a.gate_mode = h->gate_mode;
   a.z_prior = h->z_prior;
+  a.skip_events = h->numerator == 1;
   a.part = h->part.as<double>();
   const int n_tiles = (B + cfg.GL - 1) / cfg.GL;
   const int waves = cfg.waves;
@@ -452,7 +461,30 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   gs.n_split = h->n_split;
   gs.neff_min = h->neff_min;
   gs.gate_mode = h->gate_mode;
-  HIPCHK(launch_gate_split(gs, st));
+  if (h->numerator == 1) {
+    KdeArgs k;
+    k.samp = h->samp.p;
+    k.pix_off = h->pix_off.as<int64_t>();
+    k.pix_row = h->pix_row.as<int32_t>();
+    k.perm = h->perm.as<int32_t>();
+    k.los = h->los.as<float>();
+    k.n_z = h->n_z;
+    k.z_max = h->z_max;
+    k.n_pix = h->n_pix;
+    k.lamc = h->lamc.p;
+    k.cos_tab = h->cos_tab.p;
+    k.win_tab = h->win_tab.p;
+    k.B = B;
+    k.bandwidth = h->kde_bandwidth;
+    k.n_grid = h->kde_grid;
+    k.tau = 5.0;
+    k.neff_min = h->neff_min;
+    k.gate_mode = h->gate_mode;
+    k.out = h->kde_out.as<double>();
+    HIPCHK(launch_kde(h->fp32, k, h->n_cu, st));
+  } else {
+    HIPCHK(launch_gate_split(gs, st));
+  }
   if (timed) HIPCHK(hipEventRecord(h->ev[2], st));
   CombineArgs c;
   c.part = h->part.as<double>();
@@ -475,6 +507,9 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.flags = o.flags;
   c.grad = o.grad;
   c.gmap = h->gmap.as<double>();
+  c.kde = h->numerator == 1 ? h->kde_out.as<double>() : nullptr;
+  c.ev_pix_off = h->ev_pix_off.as<int64_t>();
+  c.n_pix = h->n_pix;
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -485,6 +520,9 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   (void)hipGetLastError();   // the launch checks below must not see an earlier call's error
   if (!d_lambda || !o.logL || (grad && !o.grad)) return fail(DSL_EINVAL, "NULL device pointer");
   if (B < 1 || B > h->max_batch) return fail(DSL_EINVAL, "B out of range [1, max_batch]");
+  if (h->numerator == 1 && grad) return fail(DSL_EINVAL, "the KDE numerator has no gradient (use numerator 0)");
+  if (h->numerator == 1 && h->z_prior != 0)
+    return fail(DSL_EINVAL, "the KDE numerator needs the LOS redshift tables (z_prior 0)");
   int cur = -1;
   HIPCHK(hipGetDevice(&cur));
   if (cur != h->device) return fail(DSL_ESTATE, "current device differs from the handle's device");
@@ -579,6 +617,20 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   if ((rc = upload(h->los, d->los, sizeof(float) * d->n_los_rows * (size_t)d->n_z))) return rc;
   if ((rc = upload(h->sky, d->sky_z, sizeof(float) * d->n_z))) return rc;
   if ((rc = upload(h->ln_ns, ln_ns.data(), sizeof(double) * ln_ns.size()))) return rc;
+  if ((rc = upload(h->ev_pix_off, d->event_pix_off, sizeof(int64_t) * (d->n_events + 1)))) return rc;
+  {
+    // per pixel, local sample indices in ascending d_L (ties by position): the
+    // order of the samples' redshifts for every point, used by the KDE bandwidths
+    std::vector<int32_t> perm(std::max<int64_t>(d->n_samp, 1));
+    for (int64_t j = 0; j < d->n_pix; ++j) {
+      const int64_t a = h->pso[j], n = h->pso[j + 1] - a;
+      int32_t* q = perm.data() + a;
+      for (int64_t k = 0; k < n; ++k) q[k] = (int32_t)k;
+      const double* x = d->dl + a;
+      std::sort(q, q + n, [x](int32_t u, int32_t v) { return x[u] < x[v] || (x[u] == x[v] && u < v); });
+    }
+    if ((rc = upload(h->perm, perm.data(), sizeof(int32_t) * d->n_samp))) return rc;
+  }
   if ((rc = pack_samples(h.get(), h->samp, d->m1d, d->m2d, d->dl, d->ln_pi, d->n_samp))) return rc;
   if ((rc = pack_samples(h.get(), h->inj, d->inj_m1d, d->inj_m2d, d->inj_dl, d->inj_ln_pdraw, d->n_inj))) return rc;
   for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
@@ -615,6 +667,15 @@ int dsl_set_option(dsl_handle* h, const char* key, double v) {
   } else if (k == "z_prior") {
     if (v != 0 && v != 1) return fail(DSL_EINVAL, "z_prior must be 0 (LOS tables) or 1 (comoving volume)");
     h->z_prior = (int)v;
+  } else if (k == "numerator") {
+    if (v != 0 && v != 1) return fail(DSL_EINVAL, "numerator must be 0 (per-sample sum) or 1 (KDE)");
+    h->numerator = (int)v;
+  } else if (k == "kde_bandwidth") {
+    if (v != 0 && v != 1 && v != 2) return fail(DSL_EINVAL, "kde_bandwidth must be 0 (Scott), 1 (Silverman) or 2 (biweight)");
+    h->kde_bandwidth = (int)v;
+  } else if (k == "kde_grid") {
+    if (v != (int)v || v < 2 || v > 64 * KDE_NPL_MAX) return fail(DSL_EINVAL, "kde_grid must be an integer in [2, 1024]");
+    h->kde_grid = (int)v;
   } else if (k == "timing") {
     h->timing = v != 0;
   } else if (k == "graph") {
@@ -645,6 +706,9 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "neff_min") *v = h->neff_min;
   else if (k == "gate_mode") *v = h->gate_mode;
   else if (k == "z_prior") *v = h->z_prior;
+  else if (k == "numerator") *v = h->numerator;
+  else if (k == "kde_bandwidth") *v = h->kde_bandwidth;
+  else if (k == "kde_grid") *v = h->kde_grid;
   else if (k == "max_batch") *v = h->max_batch;
   else if (k == "lambda_tile") *v = h->lambda_tile;
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
@@ -652,7 +716,8 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "lambda_tile_used") *v = h->last_gl;
   else if (k == "device_bytes") {
     *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
-                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n);
+                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_pix_off.n +
+                  h->kde_out.n);
   } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
   return DSL_OK;
 }

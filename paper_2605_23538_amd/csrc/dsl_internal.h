@@ -112,7 +112,36 @@ struct SweepArgs {
   double neff_min;
   int32_t gate_mode;
   int32_t z_prior;           // 0: LOS tables; 1: comoving volume (spectral sirens)
+  int32_t skip_events;       // 1: only the injection items (the KDE numerator sweeps events itself)
   double* part;              // [B][n_items][NF]
+};
+
+// KDE numerator: per (pixel, point) record {R, T, S1, S2}, every sum scaled by
+// 2^-R; T = integral of KDE x redshift prior x rate over the pixel's grid (0
+// when the pixel fails the gate), S1/S2 the Eq. (8) sums of its weights.
+constexpr int NF_KDE = 4;
+// Grid nodes per lane of the KDE kernel (the grid has at most 64 * KDE_NPL_MAX nodes).
+constexpr int KDE_NPL_MAX = 16;
+
+struct KdeArgs {
+  const void* samp;          // Samp<T>[n_samp]
+  const int64_t* pix_off;    // [n_pix + 1]
+  const int32_t* pix_row;    // [n_pix]
+  const int32_t* perm;       // [n_samp] per pixel: local indices in ascending d_L order
+  const float* los;          // [rows][n_z]
+  int32_t n_z;
+  double z_max;
+  int64_t n_pix;
+  const void* lamc;          // LamC<T>[B]
+  const void* cos_tab;       // [B][NU+1] of T2
+  const void* win_tab;       // [B][NW+1] of T2
+  int32_t B;
+  int32_t bandwidth;         // 0 Scott, 1 Silverman, 2 biweight
+  int32_t n_grid;            // grid nodes (2 ... 64 * KDE_NPL_MAX)
+  double tau;                // grid margin in bandwidths
+  double neff_min;
+  int32_t gate_mode;
+  double* out;               // [B][n_pix][NF_KDE]
 };
 
 struct GateSplitArgs {
@@ -146,6 +175,9 @@ struct CombineArgs {
   uint32_t* flags;              // [B] or null
   double* grad;                 // [B][16] or null
   const double* gmap;           // [B][N_GMAP] (adjoint only)
+  const double* kde;            // [B][n_pix][NF_KDE] (KDE numerator) or null
+  const int64_t* ev_pix_off;    // [n_events + 1] (KDE numerator)
+  int64_t n_pix;
 };
 
 }  // namespace dsl

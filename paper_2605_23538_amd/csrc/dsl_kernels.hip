@@ -453,18 +453,12 @@ struct TabView {
   const typename V2<T>::t* wg;     // [3][(NWG+1)][GL]
 };
 
-// Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
-// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).
-template <typename T, int GL, bool GRAD>
-__device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
-                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
-                                            T& lin_out, T* g) {
+// Eq. (1) inverted: u = d_L H0 / c = (1+z) I(z); z = u * y(v), v = sqrt(1+4u),
+// y from the point's Hermite table.
+template <typename T, int GL>
+__device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv, int lam) {
   using M = Mth<T>;
-  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
-  const T ln2 = (T)LN2;
-  // Eq. (1) inverted: u = d_L H0 / c = (1+z) I(z); z = u * y(v), v = sqrt(1+4u).
-  const T u = sp.dlc * c.H0;
-  bool ok = u <= c.u_max;
+  constexpr int NU = Tab<T>::NU;
   const T v = M::sqrt((T)1 + (T)4 * u);
   const T xv = (v - (T)1) * c.inv_hv;
   int k = (int)xv;
@@ -472,8 +466,25 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T tv_ = xv - (T)k;
   const auto A = tv.cos[k * GL + lam];
   const auto Bn = tv.cos[(k + 1) * GL + lam];
-  const T y = hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
-  const T z = u * y;
+  return u * hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
+}
+
+// Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
+// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).  With KW (the
+// KDE numerator's weights) the redshift prior and the rate are left out of w
+// and *z_out receives the sample's redshift, or -1 beyond z_max.
+template <typename T, int GL, bool GRAD, bool KW = false>
+__device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
+                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
+                                            T& lin_out, T* g, T* z_out = nullptr) {
+  static_assert(!(GRAD && KW), "the KDE weights have no adjoint");
+  using M = Mth<T>;
+  constexpr int NW = Tab<T>::NW;
+  const T ln2 = (T)LN2;
+  const T u = sp.dlc * c.H0;
+  bool ok = u <= c.u_max;
+  const T z = z_of_u<T, GL>(u, c, tv, lam);
+  if constexpr (KW) *z_out = ok ? z : (T)-1;
   const T opz = (T)1 + z;
   const T L = M::log2(opz);
   const T r = M::rcp(opz);
@@ -489,7 +500,9 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   // Redshift prior: the pixel's table, linearly interpolated (Eq. 5), or, for
   // spectral sirens (los == nullptr), the comoving-volume shape I^2 / E.
   T l0 = 0, l1 = 0, losv;
-  if (los) {
+  if constexpr (KW) {
+    losv = (T)1;
+  } else if (los) {
     const T xz = z * inv_dz;
     int kz = (int)xz;
     kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
@@ -539,12 +552,14 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T aS = M::exp2(-fabs(Y));
   const T Sf = (T)1 + aS;
   // Total: w = 2^E * los * mix / (Dp * Xf * rho * Sf).
-  const T E = c.c0 + c.gm3 * L - fmax(eX, (T)0) + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp;
+  // (KW: without psi/(1+z), whose (1+z)^(gamma-1) shares gm3 with the Jacobian's (1+z)^-2)
+  const T E = KW ? c.c0 - (T)2 * L + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp
+                 : c.c0 + c.gm3 * L - fmax(eX, (T)0) + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp;
   const T En = M::fl(E);
   const T f = E - En;
   const T eP = M::exp2(tP - mx + f), eL = M::exp2(tL - mx + f), eH = M::exp2(tH - mx + f);
   const T mixf = eP + eL + eH;
-  const T den = Dp * Xf * rho * Sf;
+  const T den = KW ? Dp * rho * Sf : Dp * Xf * rho * Sf;
   const T rden = M::rcp(den);
   T lin = losv * mixf * rden;
   ok = ok && (lin == lin) && (lin < (T)3.0e38);
@@ -831,6 +846,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
 
   for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
     const WorkItem w = a.items[a.order[it]];
+    if (a.skip_events && w.event >= 0) continue;
     ItemAcc<GRAD> chunk;
     chunk.zero();
     int npass = 0;
@@ -885,6 +901,299 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int p = 0; p < 16; ++p) out[4 + p] = chunk.G[p];
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KDE numerator (Eq. 6 inside Eq. 5; bandwidth rules of Appendix D)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rdlane(float x, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
+__device__ __forceinline__ double rdlane(double x, int j) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// Running mean and sum of squared deviations; the merge is symmetric in its
+// operands (so a butterfly leaves every lane with the same bits) and keeps an
+// exact zero spread for equal values.
+struct Welford {
+  double n, mean, m2;
+  __device__ __forceinline__ void add(double x) {
+    n += 1.0;
+    const double d = x - mean;
+    mean += d / n;
+    m2 += d * (x - mean);
+  }
+  __device__ __forceinline__ void xor_merge(int off) {
+    const double on = __shfl_xor(n, off), om = __shfl_xor(mean, off), o2 = __shfl_xor(m2, off);
+    const double nt = n + on;
+    if (nt == 0.0) return;
+    const double d = om - mean;
+    const double mm = (d == 0.0) ? mean : (n * mean + on * om) / nt;
+    m2 = (m2 + o2) + d * d * (n * on / nt);
+    mean = mm;
+    n = nt;
+  }
+};
+
+// Linear interpolation of a redshift-prior row at z in [0, z_max].
+template <typename T>
+__device__ __forceinline__ T los_at(const float* __restrict__ row, int n_z, T inv_dz, T z) {
+  const T x = z * inv_dz;
+  int k = (int)x;
+  k = k < 0 ? 0 : (k > n_z - 2 ? n_z - 2 : k);
+  const T f = x - (T)k;
+  const T l0 = (T)row[k], l1 = (T)row[k + 1];
+  return l0 + f * (l1 - l0);
+}
+
+// psi(z)/(1+z) = (1+z)^(gamma-1) / (1 + ((1+z)/(1+z_p))^(gamma+kappa)) without its constant.
+template <typename T>
+__device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
+  using M = Mth<T>;
+  const T L = M::log2((T)1 + z);
+  const T eX = c.gk * (L - c.Lp);
+  return M::exp2((c.gm3 + (T)2) * L - fmax(eX, (T)0)) * M::rcp((T)1 + M::exp2(-fabs(eX)));
+}
+
+// One wavefront per (pixel, point).  Pass A (lanes = samples): Eq. (7)
+// weights without prior and rate, Eq. (8) sums, in-support redshift moments
+// and range.  Bandwidth from the in-support redshifts (order statistics in
+// ascending d_L order, which is ascending z for any point).  Pass B (lanes =
+// grid nodes, NPL per lane): f(z_g) = sum_k w_k exp(-(z_g - z_k)^2 / 2h^2),
+// then T = dz / (h sqrt(2 pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with
+// trapezoid weights c_g.  Points of one tile (LT) share the block's tables.
+template <typename T, int LT, int NPL>
+__global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
+  using T2 = typename V2<T>::t;
+  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2* cosL = reinterpret_cast<T2*>(smem);
+  T2* winL = cosL + (NU + 1) * LT;
+  const int tile = blockIdx.y;
+  const int nl = a.B - tile * LT < LT ? a.B - tile * LT : LT;
+  const T2* cos_g = reinterpret_cast<const T2*>(a.cos_tab);
+  const T2* win_g = reinterpret_cast<const T2*>(a.win_tab);
+  for (int i = threadIdx.x; i < (NU + 1) * LT; i += blockDim.x) {
+    const int k = i / LT, l = i % LT, b = tile * LT + l;
+    cosL[i] = l < nl ? cos_g[(size_t)b * (NU + 1) + k] : T2{};
+  }
+  for (int i = threadIdx.x; i < (NW + 1) * LT; i += blockDim.x) {
+    const int k = i / LT, l = i % LT, b = tile * LT + l;
+    winL[i] = l < nl ? win_g[(size_t)b * (NW + 1) + k] : T2{};
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+  const LamC<T>* lamc = reinterpret_cast<const LamC<T>*>(a.lamc);
+  const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
+  const TabView<T> tv{cosL, winL, nullptr};
+  const T inv_dz = (T)((a.n_z - 1) / a.z_max);
+  const int64_t n_tasks = a.n_pix * nl;
+  for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
+    const int64_t p = t / nl;
+    const int l = (int)(t - p * nl);
+    const int b = tile * LT + l;
+    const LamC<T> c = lamc[b];
+    double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
+    const int64_t s0 = a.pix_off[p];
+    const int n = (int)(a.pix_off[p + 1] - s0);
+    if (!c.valid || n == 0) {
+      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
+      continue;
+    }
+    // ---- pass A
+    PixAcc<false, T> pa;
+    pa.zero();
+    Welford wf{0.0, 0.0, 0.0};
+    T zlo = (T)INFINITY, zhi = (T)-INFINITY;
+    T z1 = (T)-1, lin1 = (T)0;   // the lane's sample when n <= 64
+    int ne1 = R_SENTINEL;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int k = c0 + lane;
+      if (k < n) {
+        int ne;
+        T lin, z;
+        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+        pa.template add<T>(ne, lin, nullptr);
+        if (z >= (T)0) {
+          wf.add((double)z);
+          zlo = fmin(zlo, z);
+          zhi = fmax(zhi, z);
+        }
+        z1 = z;
+        lin1 = lin;
+        ne1 = ne;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      pa.xor_merge(off);
+      wf.xor_merge(off);
+      zlo = fmin(zlo, __shfl_xor(zlo, off));
+      zhi = fmax(zhi, __shfl_xor(zhi, off));
+    }
+    bool pass;
+    if (a.gate_mode == 2) pass = pa.S1 > 0;
+    else pass = pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
+    if (!pass) {
+      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
+      continue;
+    }
+    // ---- bandwidth (Appendix D) from the n_in in-support redshifts
+    const int nin = (int)wf.n;
+    const int R = pa.R;
+    auto zs = [&](int r) -> double {   // r-th smallest in-support redshift (uniform)
+      const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
+      return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
+    };
+    auto z_w = [&](int c0, T& z, T& w) {   // the lane's redshift and scaled weight in chunk c0
+      if (n <= 64) {
+        z = z1;
+        w = (z1 >= (T)0 && lin1 > (T)0) ? ldexp(lin1, ne1 - R) : (T)0;
+        return;
+      }
+      const int k = c0 + lane;
+      z = (T)-1;
+      w = (T)0;
+      if (k < n) {
+        int ne;
+        T lin;
+        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+        if (z >= (T)0 && lin > (T)0) w = ldexp(lin, ne - R);
+      }
+    };
+    double h = 0.0;
+    if (nin >= 2) {
+      const double sd = sqrt(wf.m2 / (double)(nin - 1));
+      const double nf = pow((double)nin, -0.2);
+      if (a.bandwidth == 0) {
+        h = 1.06 * sd * nf;
+      } else if (a.bandwidth == 1) {
+        auto q = [&](double pr) {
+          const double pos = pr * (double)(nin - 1);
+          const int i0 = (int)floor(pos);
+          const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
+          const double z0 = zs(i0);
+          return z0 + (pos - (double)i0) * (zs(i1) - z0);
+        };
+        h = 0.9 * fmin(sd, (q(0.75) - q(0.25)) / 1.34) * nf;
+      } else {
+        const int m = (nin - 1) / 2;
+        const double Q = 0.5 * (zs(m) + zs(nin / 2));
+        const int nA = m + 1, nB = nin - m - 1;
+        // k-th smallest deviation: A_i = Q - z_(m-i) and B_i = z_(m+1+i) - Q are
+        // both ascending; binary search on how many come from A.
+        auto kth = [&](int k) -> double {
+          int lo = k + 1 - nB > 0 ? k + 1 - nB : 0;
+          int hi = k + 1 < nA ? k + 1 : nA;
+          while (lo < hi) {
+            const int i = (lo + hi) >> 1, j = k + 1 - i;
+            if (Q - zs(m - i) < zs(m + j) - Q) lo = i + 1;
+            else hi = i;
+          }
+          const int j = k + 1 - lo;
+          double v = -INFINITY;
+          if (lo > 0) v = fmax(v, Q - zs(m - lo + 1));
+          if (j > 0) v = fmax(v, zs(m + j) - Q);
+          return v;
+        };
+        const double mad = 0.5 * (kth((nin - 1) / 2) + kth(nin / 2));
+        if (mad > 0.0) {
+          const double iu = 1.0 / (9.0 * mad);
+          double num = 0.0, den = 0.0;
+          for (int c0 = 0; c0 < n; c0 += 64) {
+            T z, w;
+            z_w(c0, z, w);
+            if (z >= (T)0) {
+              const double d = (double)z - Q, u = d * iu, uu = u * u;
+              if (fabs(u) < 1.0) {
+                const double om = 1.0 - uu;
+                num += d * d * (om * om) * (om * om);
+                den += om * (1.0 - 5.0 * uu);
+              }
+            }
+          }
+          num = wave_sum(num);
+          den = wave_sum(den);
+          const double bm = (double)nin * num / (den * den);
+          h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
+        }
+      }
+    }
+    const float* __restrict__ row = a.los + (size_t)a.pix_row[p] * a.n_z;
+    double Tt = 0.0;
+    if (!(h > 0.0) || !isfinite(h)) {
+      // zero bandwidth: point masses at the samples
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        T z, w;
+        z_w(c0, z, w);
+        if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(c, z));
+      }
+      Tt = wave_sum(Tt);
+    } else {
+      // ---- pass B: grid nodes g = lane + 64 i
+      const double ga = fmax(0.0, (double)zlo - a.tau * h);
+      const double gb = fmin(a.z_max, (double)zhi + a.tau * h);
+      const double dz = (gb - ga) / (double)(a.n_grid - 1);
+      const T invh = (T)(1.0 / h);
+      const T kc = (T)(-0.5 * LOG2E);
+      T zgs[NPL], vg[NPL];
+      double accd[NPL];
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int g = lane + 64 * i;
+        accd[i] = 0.0;
+        zgs[i] = (T)0;
+        vg[i] = (T)0;
+        if (g < a.n_grid) {
+          const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
+          const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
+          zgs[i] = zg * invh;
+          vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
+        }
+      }
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        T z, w;
+        z_w(c0, z, w);
+        const T zsc = z * invh;
+        const int cnt = n - c0 < 64 ? n - c0 : 64;
+        T accf[NPL];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) accf[i] = (T)0;
+        for (int j = 0; j < cnt; ++j) {
+          const T wj = rdlane(w, j);
+          if (!(wj > (T)0)) continue;
+          const T zj = rdlane(zsc, j);
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            const T x = zgs[i] - zj;
+            accf[i] = fma(wj, Mth<T>::exp2(x * x * kc), accf[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) accd[i] += (double)accf[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) Tt += (double)vg[i] * accd[i];
+      Tt = wave_sum(Tt) * dz / (h * 2.5066282746310002);
+    }
+    if (lane == 0) {
+      out[0] = (double)R;
+      out[1] = Tt;
+      out[2] = pa.S1;
+      out[3] = pa.S2;
     }
   }
 }
@@ -951,11 +1260,11 @@ __device__ inline Part3 pmerge(Part3 x, Part3 y) {
   return r;
 }
 
-template <bool GRAD>
+template <bool GRAD, bool KDE = false>
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
+  static_assert(!(GRAD && KDE), "the KDE numerator has no adjoint");
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int B = a.B;
   const double ln2 = LN2;
   const double* P = a.part;
   auto at = [&](int slot, int f) { return P[((size_t)b * a.n_items + slot) * a.nf + f]; };
@@ -976,8 +1285,16 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
 #pragma unroll
     for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
     double Rg = -1e300;
+    Part3 num{0, 0, 0};   // KDE: merged (R, sum of T) of the passing pixels
+    if constexpr (KDE) {
+      for (int64_t p = a.ev_pix_off[e]; p < a.ev_pix_off[e + 1]; ++p) {
+        const double* r = a.kde + ((size_t)b * a.n_pix + p) * NF_KDE;
+        num = pmerge(num, Part3{r[0], r[1], 0.0});
+        m = pmerge(m, Part3{r[0], r[2], r[3]});
+      }
+    }
 #pragma unroll 4
-    for (int sl = a.ev_item_off[e]; sl < a.ev_item_off[e + 1]; ++sl) {
+    for (int sl = KDE ? 0 : a.ev_item_off[e]; sl < (KDE ? 0 : a.ev_item_off[e + 1]); ++sl) {
       Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
       if constexpr (GRAD) {
         if (x.S1 > 0) {
@@ -991,8 +1308,9 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
       m = pmerge(m, x);
     }
     double lnLe, neff;
-    if (valid && m.S1 > 0) {
-      lnLe = log(m.S1) + m.R * ln2 - a.ln_ns[e];
+    if constexpr (!KDE) num = m;
+    if (valid && num.S1 > 0) {
+      lnLe = log(num.S1) + num.R * ln2 - a.ln_ns[e];
       neff = m.S1 * m.S1 / m.S2;
       if (a.gate_mode == 1 && !(neff >= a.neff_min)) {
         lnLe = -INFINITY;
@@ -1000,7 +1318,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
       }
     } else {
       lnLe = -INFINITY;
-      neff = 0;
+      neff = (valid && m.S1 > 0) ? m.S1 * m.S1 / m.S2 : 0.0;
       flags |= valid ? 2u : 0u;
     }
     if (a.logL_event) a.logL_event[(size_t)b * a.n_events + e] = lnLe;
@@ -1199,9 +1517,53 @@ static hipError_t set_attr(int fp32) {
                              (int)sweep_lds_bytes(fp32, GL, GRAD));
 }
 
-// Raise the dynamic-LDS limit of every sweep variant (once, outside any capture).
+// KDE kernel: points per block tile and its dynamic LDS.
+template <typename T> struct KdeTile { static constexpr int LT = 64; };
+template <> struct KdeTile<double> { static constexpr int LT = 4; };
+
+template <typename T>
+static size_t kde_lds_bytes() {
+  using T2 = typename V2<T>::t;
+  return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
+}
+
+template <typename T, int NPL>
+static hipError_t kde_attr() {
+  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, NPL>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
+}
+
+template <typename T>
+static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
+  constexpr int LT = KdeTile<T>::LT;
+  const int n_tiles = (a.B + LT - 1) / LT;
+  const int64_t tasks = a.n_pix * (a.B < LT ? a.B : LT);
+  int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
+  if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
+  if (grid_x < 1) grid_x = 1;
+  const dim3 grid(grid_x, n_tiles);
+  const size_t lds = kde_lds_bytes<T>();
+  if (a.n_grid <= 256) kde_kernel<T, LT, 4><<<grid, 512, lds, st>>>(a);
+  else if (a.n_grid <= 512) kde_kernel<T, LT, 8><<<grid, 512, lds, st>>>(a);
+  else if (a.n_grid <= 64 * KDE_NPL_MAX) kde_kernel<T, LT, KDE_NPL_MAX><<<grid, 512, lds, st>>>(a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st) {
+  if (a.n_pix == 0) return hipSuccess;
+  return fp32 ? kde_t<float>(a, n_cu, st) : kde_t<double>(a, n_cu, st);
+}
+
+// Raise the dynamic-LDS limit of every sweep and KDE variant (once, outside any capture).
 hipError_t init_kernel_attrs() {
   hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = kde_attr<float, 4>();
+  if (e == hipSuccess) e = kde_attr<float, 8>();
+  if (e == hipSuccess) e = kde_attr<float, KDE_NPL_MAX>();
+  if (e == hipSuccess) e = kde_attr<double, 4>();
+  if (e == hipSuccess) e = kde_attr<double, 8>();
+  if (e == hipSuccess) e = kde_attr<double, KDE_NPL_MAX>();
 #define DSL_ATTR(T, G, F)                         \
   if (e == hipSuccess) e = set_attr<T, G, true>(F); \
   if (e == hipSuccess) e = set_attr<T, G, false>(F);
@@ -1242,7 +1604,8 @@ hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
-  if (grad) combine_kernel<true><<<a.B, 256, 0, st>>>(a);
+  if (a.kde) combine_kernel<false, true><<<a.B, 256, 0, st>>>(a);
+  else if (grad) combine_kernel<true><<<a.B, 256, 0, st>>>(a);
   else combine_kernel<false><<<a.B, 256, 0, st>>>(a);
   return hipGetLastError();
 }

@@ -1,0 +1,134 @@
+"""GPU parity of the KDE numerator (Eq. 6 inside Eq. 5, Appendix D bandwidths)
+against the oracle's loglike_kde, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import TOL_LOGL_FP32, TOL_LOGL_FP64, check_events, log, need_gpu, rel_close
+from tests.test_gpu_edges import RAGGED, ragged_catalog
+
+pytestmark = pytest.mark.gpu
+BANDWIDTHS = ["scott", "silverman", "biweight"]
+
+
+@pytest.fixture(scope="module")
+def env():
+    need_gpu()
+    import torch
+    from oracle import dsl_oracle as O
+    from paper_2605_23538_amd import binding, synth
+    return dict(torch=torch, O=O, binding=binding, synth=synth, c1=synth.make_catalog("c1"))
+
+
+def _check(env, cat, lam, r, tol, **kw):
+    O = env["O"]
+    n_amb = 0
+    for b in range(len(lam)):
+        ref = O.loglike_kde(cat, lam[b], margins=True, **kw)
+        assert int(r["flags"][b]) == ref["flags"], (b, int(r["flags"][b]), ref["flags"])
+        n_amb += check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, tol)
+        if not ref["flags"]:
+            assert rel_close(float(r["logL"][b]), ref["logL"], tol), (b, float(r["logL"][b]), ref["logL"])
+            assert abs(float(r["neff_sel"][b]) - ref["neff_sel"]) <= 1e-5 * ref["neff_sel"]
+    return n_amb
+
+
+def _run(env, cat, lam, precision="fp32", **kw):
+    torch = env["torch"]
+    lik = env["binding"].DarkSirenLikelihood(cat, precision=precision, numerator="kde", **kw)
+    r = lik.loglike(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    lik.close()
+    return r
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("bandwidth", BANDWIDTHS)
+def test_config1_kde(env, precision, bandwidth):
+    """10 events x 2000 samples over 16 pixels each, 5 points (fiducial first)."""
+    synth = env["synth"]
+    log(f"[kde c1 {precision} {bandwidth}]")
+    lam = synth.draw_lambdas(5, seed=31)
+    lam[0] = synth.fiducial_lambda()
+    r = _run(env, env["c1"], lam, precision, kde_bandwidth=bandwidth)
+    tol = TOL_LOGL_FP32 if precision == "fp32" else TOL_LOGL_FP64
+    assert _check(env, env["c1"], lam, r, tol, bandwidth=bandwidth) <= 1
+
+
+@pytest.mark.parametrize("bandwidth", BANDWIDTHS)
+@pytest.mark.parametrize("gate_mode", [0, 2])
+def test_ragged_pixels_kde(env, bandwidth, gate_mode):
+    """Pixels of 0, 1, 2, 3, 7, 63, 64, 65, 130 and 200 samples: one-chunk and
+    multi-chunk passes, zero bandwidths (single samples, without the gate)."""
+    synth = env["synth"]
+    log(f"[kde ragged {bandwidth} gate {gate_mode}]")
+    cat = ragged_catalog(synth, RAGGED)
+    lam = synth.draw_lambdas(4, seed=41)
+    lam[0] = synth.fiducial_lambda()
+    r = _run(env, cat, lam, kde_bandwidth=bandwidth, gate_mode=gate_mode)
+    _check(env, cat, lam, r, TOL_LOGL_FP32, bandwidth=bandwidth, gate_mode=gate_mode)
+
+
+@pytest.mark.parametrize("n_grid", [2, 64, 300, 1024])
+def test_grid_sizes(env, n_grid):
+    """Grids below, at and above one node per lane, up to 16 nodes per lane."""
+    synth = env["synth"]
+    log(f"[kde grid {n_grid}]")
+    cat = ragged_catalog(synth, RAGGED)
+    lam = synth.fiducial_lambda()[None]
+    r = _run(env, cat, lam, kde_grid=n_grid)
+    _check(env, cat, lam, r, TOL_LOGL_FP32, n_grid=n_grid)
+
+
+def test_batch_spans_two_tiles(env):
+    """70 points: two point tiles, the second ragged."""
+    torch, O, synth = env["torch"], env["O"], env["synth"]
+    log("[kde B=70]")
+    lam = synth.draw_lambdas(70, seed=43)
+    r = _run(env, env["c1"], lam)
+    for b in (0, 1, 63, 64, 69):
+        ref = O.loglike_kde(env["c1"], lam[b], margins=True)
+        assert int(r["flags"][b]) == ref["flags"]
+        if not ref["flags"]:
+            assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32), (b, float(r["logL"][b]), ref["logL"])
+
+
+def test_full_size_pixels_subset(env):
+    """Twelve events of the 140-event catalogue (pixels of tens to hundreds of
+    samples, 1024-node tables), fiducial point, every bandwidth rule."""
+    synth = env["synth"]
+    cat = synth.make_catalog("c2").subset(np.arange(12), inj=slice(0, 200_000))
+    lam = synth.fiducial_lambda()[None]
+    for bw in BANDWIDTHS:
+        log(f"[kde c2 subset {bw}]")
+        r = _run(env, cat, lam, kde_bandwidth=bw)
+        assert _check(env, cat, lam, r, TOL_LOGL_FP32, bandwidth=bw) <= 1
+
+
+def test_kde_rejects_gradient_and_spectral(env):
+    torch, binding = env["torch"], env["binding"]
+    lam = torch.tensor(env["synth"].fiducial_lambda()[None], device="cuda")
+    lik = binding.DarkSirenLikelihood(env["c1"], numerator="kde")
+    with pytest.raises(binding.DSLError, match="no gradient"):
+        lik.loglike_grad(lam)
+    lik.set_option("z_prior", 1)
+    with pytest.raises(binding.DSLError, match="z_prior"):
+        lik.loglike(lam)
+    lik.set_option("z_prior", 0)
+    assert math.isfinite(float(lik.loglike(lam)["logL"][0]))
+    lik.close()
+
+
+def test_kde_deterministic_and_graph_replay(env):
+    torch, binding = env["torch"], env["binding"]
+    lam = torch.tensor(env["synth"].draw_lambdas(8, seed=5), device="cuda")
+    lik = binding.DarkSirenLikelihood(env["c1"], numerator="kde", kde_bandwidth="biweight")
+    lik.set_option("graph", 0)
+    ref = lik.loglike(lam)["logL"].clone()
+    lik.set_option("graph", 1)
+    for _ in range(3):
+        out = lik.loglike(lam)["logL"]
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    lik.close()
