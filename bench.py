@@ -27,6 +27,10 @@ sys.path.insert(0, ROOT)
 # counted from the source; see the design doc for the breakdown.
 FLOP_PER_WEIGHT_FWD = 175
 FLOP_PER_WEIGHT_GRAD = 360
+# KDE numerator: the weight without prior and rate (164), and per (sample, grid
+# node) kernel term: difference, scale, square, exp2, multiply-add (6).
+FLOP_PER_KDE_WEIGHT = 164
+FLOP_PER_KDE_NODE = 6
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6
@@ -50,6 +54,9 @@ def parse():
     p.add_argument("--no-single", action="store_true", help="skip the one-Lambda-per-launch comparison")
     p.add_argument("--no-autotune", action="store_true", help="use the default tile shape and chunk")
     p.add_argument("--forward-only", action="store_true")
+    p.add_argument("--numerator", default="mc", choices=["mc", "kde"],
+                   help="mc: per-sample sums (default); kde: the paper's KDE form (value only)")
+    p.add_argument("--kde-bandwidth", default="scott", choices=["scott", "silverman", "biweight"])
     p.add_argument("--copy-calib", type=int, default=0,
                    help="after the timed steps, run one elementwise copy of this many MiB (calibrates "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -57,28 +64,35 @@ def parse():
 
 
 def kernel_sha():
+    """Hash of the sweep's sources (kernel file and shared device header)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2605_23538_amd", "csrc", "dsl_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("dsl_kernels.hip", "dsl_device.h", "dsl_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_23538_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def cpu_baseline(cat, lam_row, grad):
+def cpu_baseline(cat, lam_row, grad, kde=None):
     """The oracle on a bounded sample of the workload, scaled to one full Lambda."""
     import numpy as np
     import torch
     from oracle import dsl_oracle as O
-    n_ev = 40
+    n_ev = 40 if kde is None else 8
     n_inj = 2_000_000
     sub = cat.subset(np.arange(n_ev), inj=slice(0, n_inj))
     t0 = time.perf_counter()
-    O.loglike(sub, lam_row, grad=grad)
+    if kde is None:
+        O.loglike(sub, lam_row, grad=grad)
+    else:
+        O.loglike_kde(sub, lam_row, bandwidth=kde)
     dt = time.perf_counter() - t0
     w_sub = sub.n_samp + sub.n_inj
     w_full = cat.n_samp + cat.n_inj
     per_lambda_s = dt * w_full / w_sub
     return {"value": 1.0 / per_lambda_s, "unit": "Lambda-evals/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 oracle ({'ln L + autograd gradient' if grad else 'ln L'}) on the first {n_ev} events "
+            "sample": f"FP64 oracle ({'KDE ln L, ' + kde + ' bandwidth' if kde else 'ln L + autograd gradient' if grad else 'ln L'}) on the first {n_ev} events "
                       f"({sub.n_samp} samples) and first {n_inj} injections for 1 Lambda: {dt:.2f} s, "
                       f"scaled by {w_full}/{w_sub} sample-weights to one full-catalogue Lambda"}
 
@@ -103,14 +117,16 @@ def main():
                 "c4": (64, "fp32", True), "c5": (64, "fp32", True)}[args.config]
     B = args.B or defaults[0]
     precision = args.precision or defaults[1]
-    grad = defaults[2] and not args.forward_only
+    kde = args.numerator == "kde"
+    grad = defaults[2] and not args.forward_only and not kde
     t0 = time.time()
     cat = synth.make_catalog(args.config)
     print(f"# generated {args.config}: {cat.n_events} events, {cat.n_pix} pixels, {cat.n_samp} samples, "
           f"{cat.n_inj} injections, LOS {cat.los.nbytes / 1e9:.2f} GB in {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
     t0 = time.time()
-    lik = binding.DarkSirenLikelihood(cat, precision=precision)
+    lik = binding.DarkSirenLikelihood(cat, precision=precision, numerator=args.numerator,
+                                      kde_bandwidth=args.kde_bandwidth)
     print(f"# uploaded in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     lam_np = synth.lambdas_for(args.config, B)
     lam = torch.tensor(lam_np, device="cuda:0")
@@ -143,7 +159,7 @@ def main():
 
     # timed region: K steps, HIP events around each kernel on the launch stream
     lik.set_option("timing", 1)
-    sweep_ms, setup_ms, comb_ms = [], [], []
+    sweep_ms, setup_ms, comb_ms, pix_ms = [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -152,6 +168,8 @@ def main():
         setup_ms.append(a)
         sweep_ms.append(b)
         comb_ms.append(c)
+        if kde:
+            pix_ms.append(lik.info("ms_pixels"))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lik.set_option("timing", 0)
@@ -161,23 +179,33 @@ def main():
     flags_h = flags.cpu().numpy()
     finite = int(np.isfinite(logL.cpu().numpy()).sum())
 
-    # dominant kernel: the sweep
+    # dominant kernel: the sweep (the KDE kernel with the KDE numerator)
     sweep_avg = float(np.mean(sweep_ms))
     F = FLOP_PER_WEIGHT_GRAD if grad else FLOP_PER_WEIGHT_FWD
     flops = F * n_w * B
     achieved = flops / (sweep_avg * 1e-3) / 1e12
+    if kde:
+        kde_evals = lik.info("kde_evals")
+        kde_avg = float(np.mean(pix_ms))
+        flops = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kde_evals
+        achieved = flops / (kde_avg * 1e-3) / 1e12
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
     traffic = None
     mt = MEASURED_TRAFFIC.get((args.config, B, grad))
-    if mt and precision == "fp32" and kernel_sha() == mt["kernel_sha256_16"]:
+    if mt and precision == "fp32" and not kde and kernel_sha() == mt["kernel_sha256_16"]:
         traffic = mt["bytes"]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
-                                                       int(lik.info("lambda_tile_used")), "true" if grad else "false"),
-                "kernel_ms": round(sweep_avg, 4),
+                "kernel": ("kde_kernel<%s,%d,%d>" % ("float" if precision == "fp32" else "double",
+                                                      64 if precision == "fp32" else 4,
+                                                      4 if int(lik.info("kde_grid")) <= 256 else 8)) if kde
+                else "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
+                                                 int(lik.info("lambda_tile_used")), "true" if grad else "false"),
+                "kernel_ms": round(kde_avg if kde else sweep_avg, 4),
                 "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
-                "flop_per_weight": F, "weights_per_launch": n_w * B,
+                **({"flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE,
+                    "kde_node_evals_per_launch": kde_evals, "kde_weights_per_launch": cat.n_samp * B}
+                   if kde else {"flop_per_weight": F, "weights_per_launch": n_w * B}),
                 "chunk": int(lik.info("chunk")), "items": int(lik.info("n_items"))}
 
     # one-Lambda-per-launch comparison (same kernels, B = 1, 64 launches)
@@ -221,12 +249,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline and args.config in ("c4", "c2"):
-        cpu = cpu_baseline(cat, lam_np[0], grad)
+        cpu = cpu_baseline(cat, lam_np[0], grad, args.kde_bandwidth if kde else None)
 
+    what = "log L, KDE numerator (%s)" % args.kde_bandwidth if kde else "log L + grad" if grad else "log L"
     res = {
-        "metric": ("Lambda-evaluations/sec (log L + grad) on O5-like catalogue" if grad
-                   else "Lambda-evaluations/sec (log L) on O5-like catalogue") if args.config == "c4"
-        else "Lambda-evaluations/sec (log L%s), workload %s" % (" + grad" if grad else "", args.config),
+        "metric": ("Lambda-evaluations/sec (%s) on O5-like catalogue" % what) if args.config == "c4"
+        else "Lambda-evaluations/sec (%s), workload %s" % (what, args.config),
         "value": round(value, 3), "unit": "Lambda-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if precision == "fp32" else "f64",
@@ -235,11 +263,14 @@ def main():
                                "%d Lambda per launch, %s"
                                % ({"c4": "O5-like batched (c4)"}.get(args.config, args.config), cat.n_events,
                                   cat.n_samp, cat.n_pix, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B,
-                                  "ln L + d ln L/d Lambda (16 entries)" if grad else "ln L"),
+                                  "ln L + d ln L/d Lambda (16 entries)" if grad
+                                  else "ln L with the KDE numerator (%s, %d-node grid)"
+                                  % (args.kde_bandwidth, int(lik.info("kde_grid"))) if kde else "ln L"),
                    "B": B, "precision": "FP32 weights, FP64 sums" if precision == "fp32" else "FP64"},
         "gsample_weights_per_s": round(n_w * B * args.steps / wall / 1e9, 3),
         "kernel_ms": {"setup": round(float(np.mean(setup_ms)), 4), "sweep": round(sweep_avg, 4),
-                      "combine": round(float(np.mean(comb_ms)), 4)},
+                      "combine": round(float(np.mean(comb_ms)), 4),
+                      **({"kde": round(kde_avg, 4)} if kde else {})},
         "finite_logL": finite, "flags_nonzero": int((flags_h != 0).sum()),
         "roofline": roofline, "cpu_baseline": cpu, "single_lambda_launches": single,
     }

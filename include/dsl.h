@@ -162,7 +162,10 @@ int dsl_create(const dsl_catalog_desc* desc, dsl_handle** out);
 int dsl_set_option(dsl_handle* h, const char* key, double value);
 
 /* Read back an option or a catalogue size ("n_events", "n_pix", "n_samp",
- * "n_inj", "n_items", "precision", ...).  Returns DSL_EINVAL for unknown keys. */
+ * "n_inj", "n_items", "precision", ...), or, after a call made with option
+ * "timing" = 1, "ms_sweep_only" (the weight sweep alone) and "ms_pixels" (the
+ * per-pixel stage after it: the KDE kernel, or the gate of split pixels).
+ * Returns DSL_EINVAL for unknown keys. */
 int dsl_get_info(dsl_handle* h, const char* key, double* value);
 
 /*

@@ -5,7 +5,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", "dsl_kernels.hip"), os.path.join(HERE, "csrc", "dsl_abi.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("dsl_kernels.hip", "dsl_kde.hip", "dsl_abi.cpp")]
 OUT = os.path.join(HERE, "libdsl.so")
 ARCH = os.environ.get("DSL_OFFLOAD_ARCH", "gfx950")
 

@@ -29,7 +29,10 @@ hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int gri
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
 hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st);
+hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64_t n_pix, int n_events, int B,
+                             double* ev, hipStream_t st);
 hipError_t init_kernel_attrs();
+hipError_t init_kde_attrs();
 }  // namespace dsl
 
 using namespace dsl;
@@ -112,7 +115,7 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -126,7 +129,7 @@ struct dsl_handle {
   int kde_bandwidth = 0;     // 0 Scott, 1 Silverman, 2 biweight (Appendix D)
   int kde_grid = 256;
   int last_gl = 0;           // Lambda tile of the last call
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // setup | sweep | pixels | combine
   bool have_timing = false;
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -405,6 +408,11 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
   if (h->numerator == 1 &&
       (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_pix, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
+  if (h->numerator == 1 && (e = h->kde_evals.ensure(sizeof(unsigned long long))) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (KDE counter)");
+  if (h->numerator == 1 &&
+      (e = h->kde_ev.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_events, 1))) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (KDE event terms)");
   return DSL_OK;
 }
 
@@ -452,6 +460,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   int grid_x = std::max(1, (h->n_cu * cfg.wg_per_cu + n_tiles - 1) / n_tiles);
   grid_x = std::min(grid_x, std::max(1, (h->n_items + waves - 1) / waves));
   HIPCHK(launch_sweep(h->fp32, cfg.GL, grad, a, grid_x, 64 * waves, st));
+  if (timed) HIPCHK(hipEventRecord(h->ev[4], st));
   GateSplitArgs gs;
   gs.part = h->part.as<double>();
   gs.n_items = h->n_items;
@@ -481,7 +490,10 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
     k.neff_min = h->neff_min;
     k.gate_mode = h->gate_mode;
     k.out = h->kde_out.as<double>();
+    k.evals = h->kde_evals.as<unsigned long long>();
     HIPCHK(launch_kde(h->fp32, k, h->n_cu, st));
+    HIPCHK(launch_kde_events(h->kde_out.as<double>(), h->ev_pix_off.as<int64_t>(), h->n_pix, (int)h->n_events, B,
+                             h->kde_ev.as<double>(), st));
   } else {
     HIPCHK(launch_gate_split(gs, st));
   }
@@ -507,9 +519,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.flags = o.flags;
   c.grad = o.grad;
   c.gmap = h->gmap.as<double>();
-  c.kde = h->numerator == 1 ? h->kde_out.as<double>() : nullptr;
-  c.ev_pix_off = h->ev_pix_off.as<int64_t>();
-  c.n_pix = h->n_pix;
+  c.kde = h->numerator == 1 ? h->kde_ev.as<double>() : nullptr;
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -636,6 +646,7 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
   HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIPCHK(init_kernel_attrs());
+  HIPCHK(init_kde_attrs());
   *out = h.release();
   return DSL_OK;
 }
@@ -714,10 +725,27 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
   else if (k == "n_cu") *v = h->n_cu;
   else if (k == "lambda_tile_used") *v = h->last_gl;
+  else if (k == "kde_evals") {
+    // (sample, grid node) kernel evaluations of the last KDE call (waits for the device)
+    if (!h->kde_evals.p) return fail(DSL_ESTATE, "no KDE call yet");
+    unsigned long long n = 0;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(&n, h->kde_evals.p, sizeof(n), hipMemcpyDeviceToHost));
+    *v = (double)n;
+  } else if (k == "ms_sweep_only" || k == "ms_pixels") {
+    // of the last timed call: the sweep alone, and the per-pixel stage after it
+    // (KDE kernel, or the gate of split pixels)
+    if (!h->have_timing) return fail(DSL_ESTATE, "no timed call yet (set option 'timing' to 1)");
+    HIPCHK(hipEventSynchronize(h->ev[3]));
+    float ms = 0;
+    if (k == "ms_sweep_only") HIPCHK(hipEventElapsedTime(&ms, h->ev[1], h->ev[4]));
+    else HIPCHK(hipEventElapsedTime(&ms, h->ev[4], h->ev[2]));
+    *v = ms;
+  }
   else if (k == "device_bytes") {
     *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
                   h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_pix_off.n +
-                  h->kde_out.n);
+                  h->kde_out.n + h->kde_ev.n);
   } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
   return DSL_OK;
 }

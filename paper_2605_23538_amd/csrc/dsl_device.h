@@ -1,0 +1,361 @@
+// Device code shared by the sweep and the KDE kernels: math wrappers, table
+// interpolation, the per-sample weight of Eq. (7) and exponent-tracked sums.
+#pragma once
+#include "dsl_internal.h"
+
+namespace dsl {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+template <typename T> struct Mth;
+template <> struct Mth<float> {
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float fl(float x) { return __builtin_floorf(x); }
+};
+template <> struct Mth<double> {
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double fl(double x) { return ::floor(x); }
+};
+
+template <typename T> struct Tab { static constexpr int NU = NU_F32, NW = NW_F32, NWG = NWG_F32; };
+template <> struct Tab<double> { static constexpr int NU = NU_F64, NW = NW_F64, NWG = NWG_F64; };
+
+// ---------------------------------------------------------------------------
+// per-sample weight (and optionally its log-derivatives)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T hermite(T t, T y0, T d0, T y1, T d1) {
+  const T t2 = t * t, t3 = t2 * t;
+  const T h01 = (T)3 * t2 - (T)2 * t3;
+  const T h11 = t3 - t2;
+  const T h10 = h11 - t2 + t;
+  return y0 + h01 * (y1 - y0) + h10 * d0 + h11 * d1;
+}
+template <typename T>
+__device__ __forceinline__ T hermite_dt(T t, T y0, T d0, T y1, T d1) {
+  const T t2 = t * t;
+  const T dh01 = (T)6 * (t - t2);
+  const T dh11 = (T)3 * t2 - (T)2 * t;
+  const T dh10 = dh11 - (T)2 * t + (T)1;
+  return dh01 * (y1 - y0) + dh10 * d0 + dh11 * d1;
+}
+
+// phi(x) = (e^x - 1)/x for |x| < 1/2 (Taylor, relative error < 1e-9) and its derivative.
+template <typename T>
+__device__ __forceinline__ T phi_series(T x) {
+  T p = (T)(1.0 / 40320);
+  p = p * x + (T)(1.0 / 5040);
+  p = p * x + (T)(1.0 / 720);
+  p = p * x + (T)(1.0 / 120);
+  p = p * x + (T)(1.0 / 24);
+  p = p * x + (T)(1.0 / 6);
+  p = p * x + (T)0.5;
+  return p * x + (T)1;
+}
+template <typename T>
+__device__ __forceinline__ T dphi_series(T x) {   // sum (j+1) x^j / (j+2)!
+  T p = (T)(8.0 / 362880);
+  p = p * x + (T)(7.0 / 40320);
+  p = p * x + (T)(6.0 / 5040);
+  p = p * x + (T)(5.0 / 720);
+  p = p * x + (T)(4.0 / 120);
+  p = p * x + (T)(3.0 / 24);
+  p = p * x + (T)(2.0 / 6);
+  return p * x + (T)0.5;
+}
+
+template <typename T>
+struct TabView {
+  const typename V2<T>::t* cos;   // [(NU+1)][GL]
+  const typename V2<T>::t* win;   // [(NW+1)][GL]
+  const typename V2<T>::t* wg;     // [3][(NWG+1)][GL]
+};
+
+// Eq. (1) inverted: u = d_L H0 / c = (1+z) I(z); z = u * y(v), v = sqrt(1+4u),
+// y from the point's Hermite table.
+template <typename T, int GL>
+__device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv, int lam) {
+  using M = Mth<T>;
+  constexpr int NU = Tab<T>::NU;
+  const T v = M::sqrt((T)1 + (T)4 * u);
+  const T xv = (v - (T)1) * c.inv_hv;
+  int k = (int)xv;
+  k = k < 0 ? 0 : (k > NU - 1 ? NU - 1 : k);
+  const T tv_ = xv - (T)k;
+  const auto A = tv.cos[k * GL + lam];
+  const auto Bn = tv.cos[(k + 1) * GL + lam];
+  return u * hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
+}
+
+// Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
+// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).  With KW (the
+// KDE numerator's weights) the redshift prior and the rate are left out of w
+// and *z_out receives the sample's redshift, or -1 beyond z_max.  SPEC selects
+// the comoving-volume redshift prior (spectral sirens) instead of the table.
+template <typename T, int GL, bool GRAD, bool KW = false, bool SPEC = false>
+__device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
+                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
+                                            T& lin_out, T* g, T* z_out = nullptr) {
+  static_assert(!(GRAD && KW), "the KDE weights have no adjoint");
+  using M = Mth<T>;
+  constexpr int NW = Tab<T>::NW;
+  const T ln2 = (T)LN2;
+  const T u = sp.dlc * c.H0;
+  bool ok = u <= c.u_max;
+  const T z = z_of_u<T, GL>(u, c, tv, lam);
+  if constexpr (KW) *z_out = ok ? z : (T)-1;
+  const T opz = (T)1 + z;
+  const T L = M::log2(opz);
+  const T r = M::rcp(opz);
+  const T m1 = sp.m1d * r, m2 = sp.m2d * r;
+  const T lm1 = sp.lm1d - L, lm2 = sp.lm2d - L;
+  (void)lm2;
+  ok = ok && (m1 <= c.mmax) && (m2 > c.mmin) && (m2 <= m1);
+  // Jacobian: |J| = (1+z)^2 (c/H0) D'(z), D' = I + (1+z)/E, I = u/(1+z).
+  const T E2 = c.Om * opz * opz * opz + c.OL;
+  const T rE = M::rsqrt(E2);
+  const T I = u * r;
+  const T Dp = I + opz * rE;
+  // Redshift prior: the pixel's table, linearly interpolated (Eq. 5), or, for
+  // spectral sirens, the comoving-volume shape I^2 / E.
+  T l0 = 0, l1 = 0, losv;
+  if constexpr (KW) {
+    losv = (T)1;
+  } else if constexpr (!SPEC) {
+    const T xz = z * inv_dz;
+    int kz = (int)xz;
+    kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
+    const T fz = xz - (T)kz;
+    l0 = (T)los[kz];
+    l1 = (T)los[kz + 1];
+    losv = l0 + fz * (l1 - l0);
+  } else {
+    losv = I * I * rE;
+  }
+  ok = ok && (losv > (T)0);
+  // Madau-Dickinson: psi/(1+z) = (1+z)^(gamma-1) / (1 + 2^eX).
+  const T eX = c.gk * (L - c.Lp);
+  const T aX = M::exp2(-fabs(eX));
+  const T Xf = (T)1 + aX;
+  // Mixture (in log2): power law, low peak, high peak.
+  const T tP = c.cP - c.alpha * lm1;
+  const T dLo = m1 - c.muL, dHi = m1 - c.muH;
+  const T tL = c.cL + c.kL * dLo * dLo;
+  const T tH = c.cH + c.kH * dHi * dHi;
+  const T mx = fmax(tP, fmax(tL, tH));
+  // Conditional-mass normaliser over m1^(beta+1): rho (window table or closed form).
+  const T t1 = (m1 - c.mmin) * c.inv_dm;
+  const bool inwin = t1 < (T)1;
+  const T xw = t1 * (T)NW;
+  int kw = (int)xw;
+  kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);
+  const T tw = xw - (T)kw;
+  const auto Wa = tv.win[kw * GL + lam];
+  const auto Wb = tv.win[(kw + 1) * GL + lam];
+  const T rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
+  const T ell2 = fmax(lm1 - c.lM, (T)0);       // log2(m1 / M) above the window
+  const T sl = c.s * ell2;
+  const T Em = M::exp2(-sl);                  // (M/m1)^s
+  const T xs = -sl * ln2;
+  const bool small = fabs(xs) < (T)0.5;
+  const T ellphi = small ? ell2 * ln2 * phi_series<T>(xs) : ((T)1 - Em) * c.inv_s;
+  const T rho_a = c.zw * Em + ellphi;
+  const T rho = inwin ? rho_w : rho_a;
+  ok = ok && (rho > (T)0);
+  // Smoothing of m2: S = 1/(1 + 2^Y) in window.
+  const T mp2 = m2 - c.mmin;
+  const bool w2 = mp2 < c.dm;
+  const T mq = mp2 * (mp2 - c.dm);
+  const T rq = M::rcp(mq);
+  const T Y = w2 ? c.dm * ((T)2 * mp2 - c.dm) * rq * (T)LOG2E : (T)(-1e30);
+  const T aS = M::exp2(-fabs(Y));
+  const T Sf = (T)1 + aS;
+  // Total: w = 2^E * los * mix / (Dp * Xf * rho * Sf).
+  // (KW: without psi/(1+z), whose (1+z)^(gamma-1) shares gm3 with the Jacobian's (1+z)^-2)
+  const T E = KW ? c.c0 - (T)2 * L + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp
+                 : c.c0 + c.gm3 * L - fmax(eX, (T)0) + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp;
+  const T En = M::fl(E);
+  const T f = E - En;
+  const T eP = M::exp2(tP - mx + f), eL = M::exp2(tL - mx + f), eH = M::exp2(tH - mx + f);
+  const T mixf = eP + eL + eH;
+  const T den = KW ? Dp * rho * Sf : Dp * Xf * rho * Sf;
+  const T rden = M::rcp(den);
+  T lin = losv * mixf * rden;
+  ok = ok && (lin == lin) && (lin < (T)3.0e38);
+  n_out = ok ? (int)En : R_SENTINEL;
+  lin_out = ok ? lin : (T)0;
+
+  if constexpr (GRAD) {
+    if (!ok) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) g[p] = (T)0;
+      return;
+    }
+    const T Q = M::rcp(losv * mixf);          // 1/(los mix)
+    const T rmix = Q * losv, rlos = Q * mixf;
+    const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;
+    const T rDp = rden * Xf * rho * Sf;      // 1/Dp
+    const T rXf = rden * Dp * rho * Sf;      // 1/Xf
+    const T rrho = rden * Dp * Xf * Sf;      // 1/rho
+    const T rSf = rden * Dp * Xf * rho;      // 1/Sf
+    const T lnm1 = lm1 * ln2;
+    const T lnq = sp.lq * ln2;
+    // rate pieces: sig = X/(1+X)
+    const T sig = (eX > (T)0 ? (T)1 : aX) * rXf;
+    const T lratio = (L - c.Lp) * ln2;        // ln((1+z)/(1+z_p))
+    // m1 d ln Mix / d m1
+    const T m1dmix = -c.alpha * fP - m1 * (dLo * c.isL2 * fL + dHi * c.isH2 * fH);
+    // m1 d ln rho / d m1
+    T m1dlnrho;
+    if (inwin) {
+      m1dlnrho = m1 * hermite_dt<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y) * (T)NW * c.inv_dm * rrho;
+    } else {
+      m1dlnrho = Em * ((T)1 - c.s * c.zw) * rrho;
+    }
+    // S(m2) derivatives: d ln S/dm2 = (1-S)(dm/m'^2 + dm/(m'-dm)^2)
+    T dlnS2_dm = 0, dlnS2_ddm = 0;
+    if (w2) {
+      const T omS = (Y > (T)0 ? (T)1 : aS) * rSf;
+      const T inv_mp = (mp2 - c.dm) * rq, inv_mq = mp2 * rq;   // 1/m', 1/(m'-dm)
+      dlnS2_dm = omS * c.dm * (inv_mp * inv_mp + inv_mq * inv_mq);
+      dlnS2_ddm = -omS * (inv_mp + mp2 * inv_mq * inv_mq);
+    }
+    // d ln w / dz at fixed Lambda (prior slope, rate, Jacobian, mass chain)
+    T dlnlos;
+    if constexpr (!SPEC) dlnlos = (l1 - l0) * inv_dz * rlos;
+    else dlnlos = (T)2 * rE * (I * rE * rlos) - (T)1.5 * c.Om * opz * opz * rE * rE;
+    const T Dpp = rE * ((T)2 - (T)1.5 * c.Om * opz * opz * opz * rE * rE);
+    T Gz = dlnlos + (c.gm3 - sig * c.gk) * r - Dpp * rDp;
+    Gz -= r * (m1dmix - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
+    // dz/dH0 = (d_L/c)/D', dz/dOm = -(1+z) dI/dOm / D'
+    const T dz_dH0 = sp.dlc * rDp;
+    T dI_dOm;
+    if (c.om_case == 0) {
+      const T K = (opz * rE - (T)1 + (T)0.5 * I) * c.k23;
+      dI_dOm = -(I - K) * c.hOm;
+    } else if (c.om_case == 1) {
+      dI_dOm = (T)(-0.5) * ((opz * opz * opz * opz - (T)1) * (T)0.25 - z);
+    } else {
+      const T K = ((T)1 - M::exp2((T)(-3.5) * L)) * (T)(1.0 / 3.5);
+      dI_dOm = -(I - K) * (T)0.5;
+    }
+    const T dDp_dOm = dI_dOm - (T)0.5 * opz * (opz * opz * opz - (T)1) * rE * rE * rE;
+    const T dz_dOm = -opz * dI_dOm * rDp;
+    // beta: ln q - (d rho / d beta) / rho
+    T drho_b, drho_mmin, drho_dm;
+    if (inwin) {
+      constexpr int NWG = Tab<T>::NWG;
+      const T xg = t1 * (T)NWG;
+      int kg = (int)xg;
+      kg = kg < 0 ? 0 : (kg > NWG - 1 ? NWG - 1 : kg);
+      const T tg = xg - (T)kg;
+      const auto* wg = tv.wg;
+      const auto Ga = wg[(0 * (NWG + 1) + kg) * GL + lam], Gb = wg[(0 * (NWG + 1) + kg + 1) * GL + lam];
+      const auto Ha = wg[(1 * (NWG + 1) + kg) * GL + lam], Hb = wg[(1 * (NWG + 1) + kg + 1) * GL + lam];
+      const auto Ka = wg[(2 * (NWG + 1) + kg) * GL + lam], Kb = wg[(2 * (NWG + 1) + kg + 1) * GL + lam];
+      drho_b = hermite<T>(tg, Ga.x, Ga.y, Gb.x, Gb.y);
+      drho_mmin = hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
+      drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
+    } else {
+      const T ell = ell2 * ln2;
+      // ell^2 phi'(x), x = -s ell: series, or (x e^x - e^x + 1)/s^2 with e^x = Em
+      const T l2dph = small ? ell * ell * dphi_series<T>(xs) : (xs * Em - Em + (T)1) * c.inv_s2;
+      drho_b = c.zw_beta * Em - l2dph - lnm1 * c.zw * Em;
+      drho_mmin = c.zw_mmin * Em;
+      drho_dm = c.zw_dm * Em;
+    }
+    // Basis terms: d ln w / d Lambda_p = sum_j C_pj(Lambda) b_j (+ 1/H0 for H0);
+    // the per-point coefficients C are applied once per point in combine_kernel.
+    g[0] = Gz * dz_dH0;
+    g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
+    if constexpr (SPEC) {   // explicit Omega_m dependence of ln(I^2 / E) at fixed z
+      g[1] += (T)2 * dI_dOm * (I * rE * rlos) - (T)0.5 * (opz * opz * opz - (T)1) * rE * rE;
+    }
+    g[2] = fP;
+    g[3] = fP * lnm1;
+    g[4] = lnq - drho_b * rrho;
+    g[5] = fL;
+    g[6] = fH;
+    g[7] = dlnS2_dm + drho_mmin * rrho;
+    g[8] = dlnS2_ddm - drho_dm * rrho;
+    g[9] = fL * dLo;
+    g[10] = g[9] * dLo;
+    g[11] = fH * dHi;
+    g[12] = g[11] * dHi;
+    g[13] = L;
+    g[14] = sig * lratio;
+    g[15] = sig;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exponent-tracked accumulation
+// ---------------------------------------------------------------------------
+// Pixel-level sums: S1 = sum w, S2 = sum w^2 in FP64, and (adjoint) the 16
+// basis sums sum w b_j in BT (FP32 for the FP32 sweep), all scaled by 2^-R.
+template <bool GRAD, typename BT>
+struct PixAcc {
+  int R;
+  double S1, S2;
+  BT G[GRAD ? 16 : 1];
+  __device__ __forceinline__ void zero() {
+    R = R_SENTINEL;
+    S1 = 0;
+    S2 = 0;
+#pragma unroll
+    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+  }
+  __device__ __forceinline__ void rescale(int Rn) {   // Rn >= R
+    const int d = R - Rn;
+    S1 = ldexp(S1, d);
+    S2 = ldexp(S2, 2 * d);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], d);
+    }
+    R = Rn;
+  }
+  template <typename T>
+  __device__ __forceinline__ void add(int n, T lin, const T* g) {
+    if (lin > (T)0) {
+      if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
+      else if (n > R + RESCALE_MARGIN) rescale(n);
+      const double W = ldexp((double)lin, n - R);
+      S1 += W;
+      S2 = fma(W, W, S2);
+      if constexpr (GRAD) {
+        const BT Wb = ldexp((BT)lin, n - R);
+#pragma unroll
+        for (int p = 0; p < 16; ++p) G[p] = fma(Wb, (BT)g[p], G[p]);
+      }
+    }
+  }
+  __device__ __forceinline__ void xor_merge(int off) {
+    const int Ro = __shfl_xor(R, off);
+    const double S1o = __shfl_xor(S1, off), S2o = __shfl_xor(S2, off);
+    const int Rm = R > Ro ? R : Ro;
+    const int da = R - Rm, db = Ro - Rm;
+    S1 = ldexp(S1, da) + ldexp(S1o, db);
+    S2 = ldexp(S2, 2 * da) + ldexp(S2o, 2 * db);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const BT o = __shfl_xor(G[p], off);
+        G[p] = ldexp(G[p], da) + ldexp(o, db);
+      }
+    }
+    R = Rm;
+  }
+};
+
+}  // namespace dsl

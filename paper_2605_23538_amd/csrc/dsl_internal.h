@@ -142,6 +142,7 @@ struct KdeArgs {
   double neff_min;
   int32_t gate_mode;
   double* out;               // [B][n_pix][NF_KDE]
+  unsigned long long* evals; // (sample, node) kernel evaluations of the launch (zeroed before it)
 };
 
 struct GateSplitArgs {
@@ -175,9 +176,7 @@ struct CombineArgs {
   uint32_t* flags;              // [B] or null
   double* grad;                 // [B][16] or null
   const double* gmap;           // [B][N_GMAP] (adjoint only)
-  const double* kde;            // [B][n_pix][NF_KDE] (KDE numerator) or null
-  const int64_t* ev_pix_off;    // [n_events + 1] (KDE numerator)
-  int64_t n_pix;
+  const double* kde;            // [B][n_events][NF_KDE] event records (KDE numerator) or null
 };
 
 }  // namespace dsl

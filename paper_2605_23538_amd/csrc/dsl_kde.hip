@@ -1,0 +1,418 @@
+// HIP kernels (gfx950) of the KDE numerator: the paper's per-pixel weighted
+// Gaussian KDE in redshift (Eq. 6) integrated against the pixel's redshift
+// prior and the rate on a uniform grid, with the bandwidth rules of Appendix D.
+//
+//   kde_kernel        one wavefront per (pixel, point): Eq. (7) weights, the
+//                     Eq. (8) gate, the bandwidth, the grid integral.
+//   kde_event_kernel  one wavefront per (event, point): merge of the event's
+//                     passing pixels (read by the combine kernel).
+#include "dsl_device.h"
+
+namespace dsl {
+
+// ---------------------------------------------------------------------------
+// KDE numerator (Eq. 6 inside Eq. 5; bandwidth rules of Appendix D)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rdlane(float x, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+}
+__device__ __forceinline__ double rdlane(double x, int j) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// Running mean and sum of squared deviations; the merge is symmetric in its
+// operands (so a butterfly leaves every lane with the same bits) and keeps an
+// exact zero spread for equal values.
+struct Welford {
+  double n, mean, m2;
+  __device__ __forceinline__ void add(double x) {
+    n += 1.0;
+    const double d = x - mean;
+    mean += d / n;
+    m2 += d * (x - mean);
+  }
+  __device__ __forceinline__ void xor_merge(int off) {
+    const double on = __shfl_xor(n, off), om = __shfl_xor(mean, off), o2 = __shfl_xor(m2, off);
+    const double nt = n + on;
+    if (nt == 0.0) return;
+    const double d = om - mean;
+    const double mm = (d == 0.0) ? mean : (n * mean + on * om) / nt;
+    m2 = (m2 + o2) + d * d * (n * on / nt);
+    mean = mm;
+    n = nt;
+  }
+};
+
+// Linear interpolation of a redshift-prior row at z in [0, z_max].
+template <typename T>
+__device__ __forceinline__ T los_at(const float* __restrict__ row, int n_z, T inv_dz, T z) {
+  const T x = z * inv_dz;
+  int k = (int)x;
+  k = k < 0 ? 0 : (k > n_z - 2 ? n_z - 2 : k);
+  const T f = x - (T)k;
+  const T l0 = (T)row[k], l1 = (T)row[k + 1];
+  return l0 + f * (l1 - l0);
+}
+
+// psi(z)/(1+z) = (1+z)^(gamma-1) / (1 + ((1+z)/(1+z_p))^(gamma+kappa)) without its constant.
+template <typename T>
+__device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
+  using M = Mth<T>;
+  const T L = M::log2((T)1 + z);
+  const T eX = c.gk * (L - c.Lp);
+  return M::exp2((c.gm3 + (T)2) * L - fmax(eX, (T)0)) * M::rcp((T)1 + M::exp2(-fabs(eX)));
+}
+
+// One wavefront per (pixel, point).  Pass A (lanes = samples): Eq. (7)
+// weights without prior and rate, Eq. (8) sums, in-support redshift moments
+// and range.  Bandwidth from the in-support redshifts (order statistics in
+// ascending d_L order, which is ascending z for any point).  Pass B (lanes =
+// grid nodes, NPL per lane): f(z_g) = sum_k w_k exp(-(z_g - z_k)^2 / 2h^2),
+// then T = dz / (h sqrt(2 pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with
+// trapezoid weights c_g.  Points of one tile (LT) share the block's tables.
+template <typename T, int LT, int NPL>
+__global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
+  using T2 = typename V2<T>::t;
+  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2* cosL = reinterpret_cast<T2*>(smem);
+  T2* winL = cosL + (NU + 1) * LT;
+  const int tile = blockIdx.y;
+  const int nl = a.B - tile * LT < LT ? a.B - tile * LT : LT;
+  const T2* cos_g = reinterpret_cast<const T2*>(a.cos_tab);
+  const T2* win_g = reinterpret_cast<const T2*>(a.win_tab);
+  for (int i = threadIdx.x; i < (NU + 1) * LT; i += blockDim.x) {
+    const int k = i / LT, l = i % LT, b = tile * LT + l;
+    cosL[i] = l < nl ? cos_g[(size_t)b * (NU + 1) + k] : T2{};
+  }
+  for (int i = threadIdx.x; i < (NW + 1) * LT; i += blockDim.x) {
+    const int k = i / LT, l = i % LT, b = tile * LT + l;
+    winL[i] = l < nl ? win_g[(size_t)b * (NW + 1) + k] : T2{};
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+  const LamC<T>* lamc = reinterpret_cast<const LamC<T>*>(a.lamc);
+  const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
+  const TabView<T> tv{cosL, winL, nullptr};
+  const T inv_dz = (T)((a.n_z - 1) / a.z_max);
+  const int64_t n_tasks = a.n_pix * nl;
+  unsigned long long evals = 0;   // uniform per wavefront
+  for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
+    const int64_t p = t / nl;
+    const int l = (int)(t - p * nl);
+    const int b = tile * LT + l;
+    const LamC<T> c = lamc[b];
+    double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
+    const int64_t s0 = a.pix_off[p];
+    const int n = (int)(a.pix_off[p + 1] - s0);
+    if (!c.valid || n == 0) {
+      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
+      continue;
+    }
+    // ---- pass A
+    PixAcc<false, T> pa;
+    pa.zero();
+    Welford wf{0.0, 0.0, 0.0};
+    T zlo = (T)INFINITY, zhi = (T)-INFINITY;
+    T z1 = (T)-1, lin1 = (T)0;   // the lane's sample when n <= 64
+    int ne1 = R_SENTINEL;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int k = c0 + lane;
+      if (k < n) {
+        int ne;
+        T lin, z;
+        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+        pa.template add<T>(ne, lin, nullptr);
+        if (z >= (T)0) {
+          wf.add((double)z);
+          zlo = fmin(zlo, z);
+          zhi = fmax(zhi, z);
+        }
+        z1 = z;
+        lin1 = lin;
+        ne1 = ne;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      pa.xor_merge(off);
+      wf.xor_merge(off);
+      zlo = fmin(zlo, __shfl_xor(zlo, off));
+      zhi = fmax(zhi, __shfl_xor(zhi, off));
+    }
+    bool pass;
+    if (a.gate_mode == 2) pass = pa.S1 > 0;
+    else pass = pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
+    if (!pass) {
+      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
+      continue;
+    }
+    // ---- bandwidth (Appendix D) from the n_in in-support redshifts
+    const int nin = (int)wf.n;
+    const int R = pa.R;
+    auto zs = [&](int r) -> double {   // r-th smallest in-support redshift (uniform)
+      const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
+      return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
+    };
+    auto z_w = [&](int c0, T& z, T& w) {   // the lane's redshift and scaled weight in chunk c0
+      if (n <= 64) {
+        z = z1;
+        w = (z1 >= (T)0 && lin1 > (T)0) ? ldexp(lin1, ne1 - R) : (T)0;
+        return;
+      }
+      const int k = c0 + lane;
+      z = (T)-1;
+      w = (T)0;
+      if (k < n) {
+        int ne;
+        T lin;
+        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+        if (z >= (T)0 && lin > (T)0) w = ldexp(lin, ne - R);
+      }
+    };
+    double h = 0.0;
+    if (nin >= 2) {
+      const double sd = sqrt(wf.m2 / (double)(nin - 1));
+      const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));   // n^(-1/5)
+      if (a.bandwidth == 0) {
+        h = 1.06 * sd * nf;
+      } else if (a.bandwidth == 1) {
+        auto q = [&](double pr) {
+          const double pos = pr * (double)(nin - 1);
+          const int i0 = (int)floor(pos);
+          const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
+          const double z0 = zs(i0);
+          return z0 + (pos - (double)i0) * (zs(i1) - z0);
+        };
+        h = 0.9 * fmin(sd, (q(0.75) - q(0.25)) / 1.34) * nf;
+      } else {
+        const int m = (nin - 1) / 2;
+        const double Q = 0.5 * (zs(m) + zs(nin / 2));
+        const int nA = m + 1, nB = nin - m - 1;
+        // k-th smallest deviation: A_i = Q - z_(m-i) and B_i = z_(m+1+i) - Q are
+        // both ascending; binary search on how many come from A.
+        auto kth = [&](int k) -> double {
+          int lo = k + 1 - nB > 0 ? k + 1 - nB : 0;
+          int hi = k + 1 < nA ? k + 1 : nA;
+          while (lo < hi) {
+            const int i = (lo + hi) >> 1, j = k + 1 - i;
+            if (Q - zs(m - i) < zs(m + j) - Q) lo = i + 1;
+            else hi = i;
+          }
+          const int j = k + 1 - lo;
+          double v = -INFINITY;
+          if (lo > 0) v = fmax(v, Q - zs(m - lo + 1));
+          if (j > 0) v = fmax(v, zs(m + j) - Q);
+          return v;
+        };
+        const double mad = 0.5 * (kth((nin - 1) / 2) + kth(nin / 2));
+        if (mad > 0.0) {
+          const double iu = 1.0 / (9.0 * mad);
+          double num = 0.0, den = 0.0;
+          for (int c0 = 0; c0 < n; c0 += 64) {
+            T z, w;
+            z_w(c0, z, w);
+            if (z >= (T)0) {
+              const double d = (double)z - Q, u = d * iu, uu = u * u;
+              if (fabs(u) < 1.0) {
+                const double om = 1.0 - uu;
+                num += d * d * (om * om) * (om * om);
+                den += om * (1.0 - 5.0 * uu);
+              }
+            }
+          }
+          num = wave_sum(num);
+          den = wave_sum(den);
+          const double bm = (double)nin * num / (den * den);
+          h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
+        }
+      }
+    }
+    const float* __restrict__ row = a.los + (size_t)a.pix_row[p] * a.n_z;
+    double Tt = 0.0;
+    if (!(h > 0.0) || !isfinite(h)) {
+      // zero bandwidth: point masses at the samples
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        T z, w;
+        z_w(c0, z, w);
+        if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(c, z));
+      }
+      Tt = wave_sum(Tt);
+    } else {
+      // ---- pass B: grid nodes g = lane + 64 i
+      const double ga = fmax(0.0, (double)zlo - a.tau * h);
+      const double gb = fmin(a.z_max, (double)zhi + a.tau * h);
+      const double dz = (gb - ga) / (double)(a.n_grid - 1);
+      // coordinates scaled by sqrt(log2(e)/2)/h, so each term is exp2(-(x_g - x_k)^2)
+      const T invh = (T)(sqrt(0.5 * LOG2E) / h);
+      T zgs[NPL], vg[NPL];
+      double accd[NPL];
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int g = lane + 64 * i;
+        accd[i] = 0.0;
+        zgs[i] = (T)0;
+        vg[i] = (T)0;
+        if (g < a.n_grid) {
+          const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
+          const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
+          zgs[i] = zg * invh;
+          vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
+        }
+      }
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        T z, w;
+        z_w(c0, z, w);
+        const T zsc = z * invh;
+        const int cnt = n - c0 < 64 ? n - c0 : 64;
+        T accf[NPL];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) accf[i] = (T)0;
+        evals += (unsigned long long)__popcll(__ballot(w > (T)0)) * (unsigned long long)a.n_grid;
+        // zero weights (out of support) add exact zeros: no per-sample branch
+        for (int j = 0; j < cnt; ++j) {
+          const T wj = rdlane(w, j);
+          const T zj = rdlane(zsc, j);
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            const T x = zgs[i] - zj;
+            accf[i] = fma(wj, Mth<T>::exp2(-(x * x)), accf[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) accd[i] += (double)accf[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) Tt += (double)vg[i] * accd[i];
+      Tt = wave_sum(Tt) * dz / (h * 2.5066282746310002);
+    }
+    if (lane == 0) {
+      out[0] = (double)R;
+      out[1] = Tt;
+      out[2] = pa.S1;
+      out[3] = pa.S2;
+    }
+  }
+  if (a.evals && lane == 0 && evals) atomicAdd(a.evals, evals);
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+// Per (event, point): merge the event's pixel records {R, T, S1, S2} (pixels
+// with S1 > 0, i.e. passing the gate) under one exponent.  One wavefront per
+// pair; lanes stride over the pixels, then a symmetric butterfly.
+__global__ __launch_bounds__(256) void kde_event_kernel(const double* __restrict__ pix, const int64_t* ev_pix_off,
+                                                        int64_t n_pix, int n_events, int B, double* __restrict__ ev) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= (int64_t)n_events * B) return;
+  const int b = (int)(w / n_events), e = (int)(w % n_events);
+  int R = R_SENTINEL;
+  double T = 0, S1 = 0, S2 = 0;
+  for (int64_t p = ev_pix_off[e] + lane; p < ev_pix_off[e + 1]; p += 64) {
+    const double* r = pix + ((size_t)b * n_pix + p) * NF_KDE;
+    if (!(r[2] > 0)) continue;
+    const int Rp = (int)r[0];
+    if (R == R_SENTINEL) R = Rp;
+    else if (Rp > R) {
+      T = ldexp(T, R - Rp);
+      S1 = ldexp(S1, R - Rp);
+      S2 = ldexp(S2, 2 * (R - Rp));
+      R = Rp;
+    }
+    T += ldexp(r[1], Rp - R);
+    S1 += ldexp(r[2], Rp - R);
+    S2 += ldexp(r[3], 2 * (Rp - R));
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int Ro = __shfl_xor(R, off);
+    const double To = __shfl_xor(T, off), S1o = __shfl_xor(S1, off), S2o = __shfl_xor(S2, off);
+    const int Rm = R > Ro ? R : Ro;
+    T = ldexp(T, R - Rm) + ldexp(To, Ro - Rm);
+    S1 = ldexp(S1, R - Rm) + ldexp(S1o, Ro - Rm);
+    S2 = ldexp(S2, 2 * (R - Rm)) + ldexp(S2o, 2 * (Ro - Rm));
+    R = Rm;
+  }
+  if (lane == 0) {
+    double* o = ev + ((size_t)b * n_events + e) * NF_KDE;
+    o[0] = (double)R;
+    o[1] = T;
+    o[2] = S1;
+    o[3] = S2;
+  }
+}
+
+// KDE kernel: points per block tile and its dynamic LDS.
+template <typename T> struct KdeTile { static constexpr int LT = 64; };
+template <> struct KdeTile<double> { static constexpr int LT = 4; };
+
+template <typename T>
+static size_t kde_lds_bytes() {
+  using T2 = typename V2<T>::t;
+  return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
+}
+
+template <typename T, int NPL>
+static hipError_t kde_attr() {
+  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, NPL>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
+}
+
+template <typename T>
+static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
+  constexpr int LT = KdeTile<T>::LT;
+  const int n_tiles = (a.B + LT - 1) / LT;
+  const int64_t tasks = a.n_pix * (a.B < LT ? a.B : LT);
+  int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
+  if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
+  if (grid_x < 1) grid_x = 1;
+  const dim3 grid(grid_x, n_tiles);
+  const size_t lds = kde_lds_bytes<T>();
+  if (a.n_grid <= 256) kde_kernel<T, LT, 4><<<grid, 512, lds, st>>>(a);
+  else if (a.n_grid <= 512) kde_kernel<T, LT, 8><<<grid, 512, lds, st>>>(a);
+  else if (a.n_grid <= 64 * KDE_NPL_MAX) kde_kernel<T, LT, KDE_NPL_MAX><<<grid, 512, lds, st>>>(a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st) {
+  if (a.evals) {
+    zero_u64_kernel<<<1, 64, 0, st>>>(a.evals);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.n_pix == 0) return hipSuccess;
+  return fp32 ? kde_t<float>(a, n_cu, st) : kde_t<double>(a, n_cu, st);
+}
+
+hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64_t n_pix, int n_events, int B,
+                             double* ev, hipStream_t st) {
+  const int64_t threads = (int64_t)n_events * B * 64;
+  kde_event_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(pix, ev_pix_off, n_pix, n_events, B, ev);
+  return hipGetLastError();
+}
+
+// Raise the dynamic-LDS limit of every KDE variant (once, outside any capture).
+hipError_t init_kde_attrs() {
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = kde_attr<float, 4>();
+  if (e == hipSuccess) e = kde_attr<float, 8>();
+  if (e == hipSuccess) e = kde_attr<float, KDE_NPL_MAX>();
+  if (e == hipSuccess) e = kde_attr<double, 4>();
+  if (e == hipSuccess) e = kde_attr<double, 8>();
+  if (e == hipSuccess) e = kde_attr<double, KDE_NPL_MAX>();
+  return e;
+}
+
+}  // namespace dsl

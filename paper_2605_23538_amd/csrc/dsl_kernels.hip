@@ -14,34 +14,9 @@
 // factor that can over- or underflow (prior, power laws, smoothing tails) is
 // added into the binary exponent, and FP64 sums are rescaled by exact powers
 // of two: the log-sum-exp needs no transcendental per merge.
-#include "dsl_internal.h"
+#include "dsl_device.h"
 
 namespace dsl {
-
-template <typename T> struct V2;
-template <> struct V2<float> { using t = float2; };
-template <> struct V2<double> { using t = double2; };
-
-template <typename T> struct Mth;
-template <> struct Mth<float> {
-  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
-  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
-  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-  static __device__ __forceinline__ float fl(float x) { return __builtin_floorf(x); }
-};
-template <> struct Mth<double> {
-  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
-  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
-  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-  static __device__ __forceinline__ double fl(double x) { return ::floor(x); }
-};
-
-template <typename T> struct Tab { static constexpr int NU = NU_F32, NW = NW_F32, NWG = NWG_F32; };
-template <> struct Tab<double> { static constexpr int NU = NU_F64, NW = NW_F64, NWG = NWG_F64; };
 
 // ---------------------------------------------------------------------------
 // FP64 helpers of the setup kernel
@@ -402,332 +377,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   }
 }
 
-// ---------------------------------------------------------------------------
-// per-sample weight (and optionally its log-derivatives)
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T hermite(T t, T y0, T d0, T y1, T d1) {
-  const T t2 = t * t, t3 = t2 * t;
-  const T h01 = (T)3 * t2 - (T)2 * t3;
-  const T h11 = t3 - t2;
-  const T h10 = h11 - t2 + t;
-  return y0 + h01 * (y1 - y0) + h10 * d0 + h11 * d1;
-}
-template <typename T>
-__device__ __forceinline__ T hermite_dt(T t, T y0, T d0, T y1, T d1) {
-  const T t2 = t * t;
-  const T dh01 = (T)6 * (t - t2);
-  const T dh11 = (T)3 * t2 - (T)2 * t;
-  const T dh10 = dh11 - (T)2 * t + (T)1;
-  return dh01 * (y1 - y0) + dh10 * d0 + dh11 * d1;
-}
-
-// phi(x) = (e^x - 1)/x for |x| < 1/2 (Taylor, relative error < 1e-9) and its derivative.
-template <typename T>
-__device__ __forceinline__ T phi_series(T x) {
-  T p = (T)(1.0 / 40320);
-  p = p * x + (T)(1.0 / 5040);
-  p = p * x + (T)(1.0 / 720);
-  p = p * x + (T)(1.0 / 120);
-  p = p * x + (T)(1.0 / 24);
-  p = p * x + (T)(1.0 / 6);
-  p = p * x + (T)0.5;
-  return p * x + (T)1;
-}
-template <typename T>
-__device__ __forceinline__ T dphi_series(T x) {   // sum (j+1) x^j / (j+2)!
-  T p = (T)(8.0 / 362880);
-  p = p * x + (T)(7.0 / 40320);
-  p = p * x + (T)(6.0 / 5040);
-  p = p * x + (T)(5.0 / 720);
-  p = p * x + (T)(4.0 / 120);
-  p = p * x + (T)(3.0 / 24);
-  p = p * x + (T)(2.0 / 6);
-  return p * x + (T)0.5;
-}
-
-template <typename T>
-struct TabView {
-  const typename V2<T>::t* cos;   // [(NU+1)][GL]
-  const typename V2<T>::t* win;   // [(NW+1)][GL]
-  const typename V2<T>::t* wg;     // [3][(NWG+1)][GL]
-};
-
-// Eq. (1) inverted: u = d_L H0 / c = (1+z) I(z); z = u * y(v), v = sqrt(1+4u),
-// y from the point's Hermite table.
-template <typename T, int GL>
-__device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv, int lam) {
-  using M = Mth<T>;
-  constexpr int NU = Tab<T>::NU;
-  const T v = M::sqrt((T)1 + (T)4 * u);
-  const T xv = (v - (T)1) * c.inv_hv;
-  int k = (int)xv;
-  k = k < 0 ? 0 : (k > NU - 1 ? NU - 1 : k);
-  const T tv_ = xv - (T)k;
-  const auto A = tv.cos[k * GL + lam];
-  const auto Bn = tv.cos[(k + 1) * GL + lam];
-  return u * hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
-}
-
-// Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
-// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).  With KW (the
-// KDE numerator's weights) the redshift prior and the rate are left out of w
-// and *z_out receives the sample's redshift, or -1 beyond z_max.
-template <typename T, int GL, bool GRAD, bool KW = false>
-__device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
-                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
-                                            T& lin_out, T* g, T* z_out = nullptr) {
-  static_assert(!(GRAD && KW), "the KDE weights have no adjoint");
-  using M = Mth<T>;
-  constexpr int NW = Tab<T>::NW;
-  const T ln2 = (T)LN2;
-  const T u = sp.dlc * c.H0;
-  bool ok = u <= c.u_max;
-  const T z = z_of_u<T, GL>(u, c, tv, lam);
-  if constexpr (KW) *z_out = ok ? z : (T)-1;
-  const T opz = (T)1 + z;
-  const T L = M::log2(opz);
-  const T r = M::rcp(opz);
-  const T m1 = sp.m1d * r, m2 = sp.m2d * r;
-  const T lm1 = sp.lm1d - L, lm2 = sp.lm2d - L;
-  (void)lm2;
-  ok = ok && (m1 <= c.mmax) && (m2 > c.mmin) && (m2 <= m1);
-  // Jacobian: |J| = (1+z)^2 (c/H0) D'(z), D' = I + (1+z)/E, I = u/(1+z).
-  const T E2 = c.Om * opz * opz * opz + c.OL;
-  const T rE = M::rsqrt(E2);
-  const T I = u * r;
-  const T Dp = I + opz * rE;
-  // Redshift prior: the pixel's table, linearly interpolated (Eq. 5), or, for
-  // spectral sirens (los == nullptr), the comoving-volume shape I^2 / E.
-  T l0 = 0, l1 = 0, losv;
-  if constexpr (KW) {
-    losv = (T)1;
-  } else if (los) {
-    const T xz = z * inv_dz;
-    int kz = (int)xz;
-    kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
-    const T fz = xz - (T)kz;
-    l0 = (T)los[kz];
-    l1 = (T)los[kz + 1];
-    losv = l0 + fz * (l1 - l0);
-  } else {
-    losv = I * I * rE;
-  }
-  ok = ok && (losv > (T)0);
-  // Madau-Dickinson: psi/(1+z) = (1+z)^(gamma-1) / (1 + 2^eX).
-  const T eX = c.gk * (L - c.Lp);
-  const T aX = M::exp2(-fabs(eX));
-  const T Xf = (T)1 + aX;
-  // Mixture (in log2): power law, low peak, high peak.
-  const T tP = c.cP - c.alpha * lm1;
-  const T dLo = m1 - c.muL, dHi = m1 - c.muH;
-  const T tL = c.cL + c.kL * dLo * dLo;
-  const T tH = c.cH + c.kH * dHi * dHi;
-  const T mx = fmax(tP, fmax(tL, tH));
-  // Conditional-mass normaliser over m1^(beta+1): rho (window table or closed form).
-  const T t1 = (m1 - c.mmin) * c.inv_dm;
-  const bool inwin = t1 < (T)1;
-  const T xw = t1 * (T)NW;
-  int kw = (int)xw;
-  kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);
-  const T tw = xw - (T)kw;
-  const auto Wa = tv.win[kw * GL + lam];
-  const auto Wb = tv.win[(kw + 1) * GL + lam];
-  const T rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
-  const T ell2 = fmax(lm1 - c.lM, (T)0);       // log2(m1 / M) above the window
-  const T sl = c.s * ell2;
-  const T Em = M::exp2(-sl);                  // (M/m1)^s
-  const T xs = -sl * ln2;
-  const bool small = fabs(xs) < (T)0.5;
-  const T ellphi = small ? ell2 * ln2 * phi_series<T>(xs) : ((T)1 - Em) * c.inv_s;
-  const T rho_a = c.zw * Em + ellphi;
-  const T rho = inwin ? rho_w : rho_a;
-  ok = ok && (rho > (T)0);
-  // Smoothing of m2: S = 1/(1 + 2^Y) in window.
-  const T mp2 = m2 - c.mmin;
-  const bool w2 = mp2 < c.dm;
-  const T mq = mp2 * (mp2 - c.dm);
-  const T rq = M::rcp(mq);
-  const T Y = w2 ? c.dm * ((T)2 * mp2 - c.dm) * rq * (T)LOG2E : (T)(-1e30);
-  const T aS = M::exp2(-fabs(Y));
-  const T Sf = (T)1 + aS;
-  // Total: w = 2^E * los * mix / (Dp * Xf * rho * Sf).
-  // (KW: without psi/(1+z), whose (1+z)^(gamma-1) shares gm3 with the Jacobian's (1+z)^-2)
-  const T E = KW ? c.c0 - (T)2 * L + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp
-                 : c.c0 + c.gm3 * L - fmax(eX, (T)0) + mx + c.beta * sp.lq - lm1 - fmax(Y, (T)0) + sp.nlp;
-  const T En = M::fl(E);
-  const T f = E - En;
-  const T eP = M::exp2(tP - mx + f), eL = M::exp2(tL - mx + f), eH = M::exp2(tH - mx + f);
-  const T mixf = eP + eL + eH;
-  const T den = KW ? Dp * rho * Sf : Dp * Xf * rho * Sf;
-  const T rden = M::rcp(den);
-  T lin = losv * mixf * rden;
-  ok = ok && (lin == lin) && (lin < (T)3.0e38);
-  n_out = ok ? (int)En : R_SENTINEL;
-  lin_out = ok ? lin : (T)0;
-
-  if constexpr (GRAD) {
-    if (!ok) {
-#pragma unroll
-      for (int p = 0; p < 16; ++p) g[p] = (T)0;
-      return;
-    }
-    const T Q = M::rcp(losv * mixf);          // 1/(los mix)
-    const T rmix = Q * losv, rlos = Q * mixf;
-    const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;
-    const T rDp = rden * Xf * rho * Sf;      // 1/Dp
-    const T rXf = rden * Dp * rho * Sf;      // 1/Xf
-    const T rrho = rden * Dp * Xf * Sf;      // 1/rho
-    const T rSf = rden * Dp * Xf * rho;      // 1/Sf
-    const T lnm1 = lm1 * ln2;
-    const T lnq = sp.lq * ln2;
-    // rate pieces: sig = X/(1+X)
-    const T sig = (eX > (T)0 ? (T)1 : aX) * rXf;
-    const T lratio = (L - c.Lp) * ln2;        // ln((1+z)/(1+z_p))
-    // m1 d ln Mix / d m1
-    const T m1dmix = -c.alpha * fP - m1 * (dLo * c.isL2 * fL + dHi * c.isH2 * fH);
-    // m1 d ln rho / d m1
-    T m1dlnrho;
-    if (inwin) {
-      m1dlnrho = m1 * hermite_dt<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y) * (T)NW * c.inv_dm * rrho;
-    } else {
-      m1dlnrho = Em * ((T)1 - c.s * c.zw) * rrho;
-    }
-    // S(m2) derivatives: d ln S/dm2 = (1-S)(dm/m'^2 + dm/(m'-dm)^2)
-    T dlnS2_dm = 0, dlnS2_ddm = 0;
-    if (w2) {
-      const T omS = (Y > (T)0 ? (T)1 : aS) * rSf;
-      const T inv_mp = (mp2 - c.dm) * rq, inv_mq = mp2 * rq;   // 1/m', 1/(m'-dm)
-      dlnS2_dm = omS * c.dm * (inv_mp * inv_mp + inv_mq * inv_mq);
-      dlnS2_ddm = -omS * (inv_mp + mp2 * inv_mq * inv_mq);
-    }
-    // d ln w / dz at fixed Lambda (prior slope, rate, Jacobian, mass chain)
-    const T dlnlos = los ? (l1 - l0) * inv_dz * rlos
-                         : (T)2 * rE * (I * rE * rlos) - (T)1.5 * c.Om * opz * opz * rE * rE;
-    const T Dpp = rE * ((T)2 - (T)1.5 * c.Om * opz * opz * opz * rE * rE);
-    T Gz = dlnlos + (c.gm3 - sig * c.gk) * r - Dpp * rDp;
-    Gz -= r * (m1dmix - ((T)1 + m1dlnrho) + m2 * dlnS2_dm);
-    // dz/dH0 = (d_L/c)/D', dz/dOm = -(1+z) dI/dOm / D'
-    const T dz_dH0 = sp.dlc * rDp;
-    T dI_dOm;
-    if (c.om_case == 0) {
-      const T K = (opz * rE - (T)1 + (T)0.5 * I) * c.k23;
-      dI_dOm = -(I - K) * c.hOm;
-    } else if (c.om_case == 1) {
-      dI_dOm = (T)(-0.5) * ((opz * opz * opz * opz - (T)1) * (T)0.25 - z);
-    } else {
-      const T K = ((T)1 - M::exp2((T)(-3.5) * L)) * (T)(1.0 / 3.5);
-      dI_dOm = -(I - K) * (T)0.5;
-    }
-    const T dDp_dOm = dI_dOm - (T)0.5 * opz * (opz * opz * opz - (T)1) * rE * rE * rE;
-    const T dz_dOm = -opz * dI_dOm * rDp;
-    // beta: ln q - (d rho / d beta) / rho
-    T drho_b, drho_mmin, drho_dm;
-    if (inwin) {
-      constexpr int NWG = Tab<T>::NWG;
-      const T xg = t1 * (T)NWG;
-      int kg = (int)xg;
-      kg = kg < 0 ? 0 : (kg > NWG - 1 ? NWG - 1 : kg);
-      const T tg = xg - (T)kg;
-      const auto* wg = tv.wg;
-      const auto Ga = wg[(0 * (NWG + 1) + kg) * GL + lam], Gb = wg[(0 * (NWG + 1) + kg + 1) * GL + lam];
-      const auto Ha = wg[(1 * (NWG + 1) + kg) * GL + lam], Hb = wg[(1 * (NWG + 1) + kg + 1) * GL + lam];
-      const auto Ka = wg[(2 * (NWG + 1) + kg) * GL + lam], Kb = wg[(2 * (NWG + 1) + kg + 1) * GL + lam];
-      drho_b = hermite<T>(tg, Ga.x, Ga.y, Gb.x, Gb.y);
-      drho_mmin = hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
-      drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
-    } else {
-      const T ell = ell2 * ln2;
-      // ell^2 phi'(x), x = -s ell: series, or (x e^x - e^x + 1)/s^2 with e^x = Em
-      const T l2dph = small ? ell * ell * dphi_series<T>(xs) : (xs * Em - Em + (T)1) * c.inv_s2;
-      drho_b = c.zw_beta * Em - l2dph - lnm1 * c.zw * Em;
-      drho_mmin = c.zw_mmin * Em;
-      drho_dm = c.zw_dm * Em;
-    }
-    // Basis terms: d ln w / d Lambda_p = sum_j C_pj(Lambda) b_j (+ 1/H0 for H0);
-    // the per-point coefficients C are applied once per point in combine_kernel.
-    g[0] = Gz * dz_dH0;
-    g[1] = -dDp_dOm * rDp + Gz * dz_dOm;
-    if (!los) {   // explicit Omega_m dependence of ln(I^2 / E) at fixed z
-      g[1] += (T)2 * dI_dOm * (I * rE * rlos) - (T)0.5 * (opz * opz * opz - (T)1) * rE * rE;
-    }
-    g[2] = fP;
-    g[3] = fP * lnm1;
-    g[4] = lnq - drho_b * rrho;
-    g[5] = fL;
-    g[6] = fH;
-    g[7] = dlnS2_dm + drho_mmin * rrho;
-    g[8] = dlnS2_ddm - drho_dm * rrho;
-    g[9] = fL * dLo;
-    g[10] = g[9] * dLo;
-    g[11] = fH * dHi;
-    g[12] = g[11] * dHi;
-    g[13] = L;
-    g[14] = sig * lratio;
-    g[15] = sig;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// exponent-tracked accumulation
-// ---------------------------------------------------------------------------
-// Pixel-level sums: S1 = sum w, S2 = sum w^2 in FP64, and (adjoint) the 16
-// basis sums sum w b_j in BT (FP32 for the FP32 sweep), all scaled by 2^-R.
-template <bool GRAD, typename BT>
-struct PixAcc {
-  int R;
-  double S1, S2;
-  BT G[GRAD ? 16 : 1];
-  __device__ __forceinline__ void zero() {
-    R = R_SENTINEL;
-    S1 = 0;
-    S2 = 0;
-#pragma unroll
-    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
-  }
-  __device__ __forceinline__ void rescale(int Rn) {   // Rn >= R
-    const int d = R - Rn;
-    S1 = ldexp(S1, d);
-    S2 = ldexp(S2, 2 * d);
-    if constexpr (GRAD) {
-#pragma unroll
-      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], d);
-    }
-    R = Rn;
-  }
-  template <typename T>
-  __device__ __forceinline__ void add(int n, T lin, const T* g) {
-    if (lin > (T)0) {
-      if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
-      else if (n > R + RESCALE_MARGIN) rescale(n);
-      const double W = ldexp((double)lin, n - R);
-      S1 += W;
-      S2 = fma(W, W, S2);
-      if constexpr (GRAD) {
-        const BT Wb = ldexp((BT)lin, n - R);
-#pragma unroll
-        for (int p = 0; p < 16; ++p) G[p] = fma(Wb, (BT)g[p], G[p]);
-      }
-    }
-  }
-  __device__ __forceinline__ void xor_merge(int off) {
-    const int Ro = __shfl_xor(R, off);
-    const double S1o = __shfl_xor(S1, off), S2o = __shfl_xor(S2, off);
-    const int Rm = R > Ro ? R : Ro;
-    const int da = R - Rm, db = Ro - Rm;
-    S1 = ldexp(S1, da) + ldexp(S1o, db);
-    S2 = ldexp(S2, 2 * da) + ldexp(S2o, 2 * db);
-    if constexpr (GRAD) {
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const BT o = __shfl_xor(G[p], off);
-        G[p] = ldexp(G[p], da) + ldexp(o, db);
-      }
-    }
-    R = Rm;
-  }
-};
-
 // Item-level sums (FP64 throughout).
 template <bool GRAD>
 struct ItemAcc {
@@ -771,7 +420,7 @@ __device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_
 
 // One run of samples [s0, s1) accumulated into acc; the next record is
 // loaded while the current one is evaluated.
-template <typename T, int GL, bool GRAD, typename AccT>
+template <typename T, int GL, bool GRAD, bool SPEC, typename AccT>
 __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
                                           bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
                                           const float* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
@@ -788,7 +437,7 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
     if (sb + sg < s1 && live) {
       int n;
       T lin;
-      eval_weight<T, GL, GRAD>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g);
+      eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g);
       acc.template add<T>(n, lin, g);
     }
   }
@@ -797,7 +446,7 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
 // ---------------------------------------------------------------------------
 // sweep
 // ---------------------------------------------------------------------------
-template <typename T, int GL, bool GRAD>
+template <typename T, int GL, bool GRAD, bool SPEC>
 __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
@@ -852,20 +501,20 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
     int npass = 0;
     if (w.event >= 0 && w.pix1 == w.pix0) {
       // part of a large pixel: ungated sums, gated after the sweep (gate_split_kernel)
-      const float* __restrict__ tab = a.z_prior ? nullptr : a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
+      const float* __restrict__ tab = SPEC ? nullptr : a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
       PixAcc<GRAD, T> pix;
       pix.zero();
-      sweep_run<T, GL, GRAD>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
+      sweep_run<T, GL, GRAD, SPEC>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
 #pragma unroll
       for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
       chunk.merge(pix);
     } else if (w.event >= 0) {
       for (int p = w.pix0; p < w.pix1; ++p) {
         const int64_t s0 = a.pix_off[p], s1 = a.pix_off[p + 1];
-        const float* __restrict__ tab = a.z_prior ? nullptr : a.los + (size_t)a.pix_row[p] * a.n_z;
+        const float* __restrict__ tab = SPEC ? nullptr : a.los + (size_t)a.pix_row[p] * a.n_z;
         PixAcc<GRAD, T> pix;
         pix.zero();
-        sweep_run<T, GL, GRAD>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
+        sweep_run<T, GL, GRAD, SPEC>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         bool pass;
@@ -883,7 +532,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
         PixAcc<GRAD, T> pix;
         pix.zero();
         const int64_t v1 = v0 + VP < w.s1 ? v0 + VP : w.s1;
-        sweep_run<T, GL, GRAD>(inj, v0, v1, sg, live, c, tv, lam, a.z_prior ? nullptr : a.sky, a.n_z, inv_dz,
+        sweep_run<T, GL, GRAD, SPEC>(inj, v0, v1, sg, live, c, tv, lam, SPEC ? nullptr : a.sky, a.n_z, inv_dz,
                                pix, g);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
@@ -901,299 +550,6 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int p = 0; p < 16; ++p) out[4 + p] = chunk.G[p];
       }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// KDE numerator (Eq. 6 inside Eq. 5; bandwidth rules of Appendix D)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float rdlane(float x, int j) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-}
-__device__ __forceinline__ double rdlane(double x, int j) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-// Running mean and sum of squared deviations; the merge is symmetric in its
-// operands (so a butterfly leaves every lane with the same bits) and keeps an
-// exact zero spread for equal values.
-struct Welford {
-  double n, mean, m2;
-  __device__ __forceinline__ void add(double x) {
-    n += 1.0;
-    const double d = x - mean;
-    mean += d / n;
-    m2 += d * (x - mean);
-  }
-  __device__ __forceinline__ void xor_merge(int off) {
-    const double on = __shfl_xor(n, off), om = __shfl_xor(mean, off), o2 = __shfl_xor(m2, off);
-    const double nt = n + on;
-    if (nt == 0.0) return;
-    const double d = om - mean;
-    const double mm = (d == 0.0) ? mean : (n * mean + on * om) / nt;
-    m2 = (m2 + o2) + d * d * (n * on / nt);
-    mean = mm;
-    n = nt;
-  }
-};
-
-// Linear interpolation of a redshift-prior row at z in [0, z_max].
-template <typename T>
-__device__ __forceinline__ T los_at(const float* __restrict__ row, int n_z, T inv_dz, T z) {
-  const T x = z * inv_dz;
-  int k = (int)x;
-  k = k < 0 ? 0 : (k > n_z - 2 ? n_z - 2 : k);
-  const T f = x - (T)k;
-  const T l0 = (T)row[k], l1 = (T)row[k + 1];
-  return l0 + f * (l1 - l0);
-}
-
-// psi(z)/(1+z) = (1+z)^(gamma-1) / (1 + ((1+z)/(1+z_p))^(gamma+kappa)) without its constant.
-template <typename T>
-__device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
-  using M = Mth<T>;
-  const T L = M::log2((T)1 + z);
-  const T eX = c.gk * (L - c.Lp);
-  return M::exp2((c.gm3 + (T)2) * L - fmax(eX, (T)0)) * M::rcp((T)1 + M::exp2(-fabs(eX)));
-}
-
-// One wavefront per (pixel, point).  Pass A (lanes = samples): Eq. (7)
-// weights without prior and rate, Eq. (8) sums, in-support redshift moments
-// and range.  Bandwidth from the in-support redshifts (order statistics in
-// ascending d_L order, which is ascending z for any point).  Pass B (lanes =
-// grid nodes, NPL per lane): f(z_g) = sum_k w_k exp(-(z_g - z_k)^2 / 2h^2),
-// then T = dz / (h sqrt(2 pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with
-// trapezoid weights c_g.  Points of one tile (LT) share the block's tables.
-template <typename T, int LT, int NPL>
-__global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
-  using T2 = typename V2<T>::t;
-  constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T2* cosL = reinterpret_cast<T2*>(smem);
-  T2* winL = cosL + (NU + 1) * LT;
-  const int tile = blockIdx.y;
-  const int nl = a.B - tile * LT < LT ? a.B - tile * LT : LT;
-  const T2* cos_g = reinterpret_cast<const T2*>(a.cos_tab);
-  const T2* win_g = reinterpret_cast<const T2*>(a.win_tab);
-  for (int i = threadIdx.x; i < (NU + 1) * LT; i += blockDim.x) {
-    const int k = i / LT, l = i % LT, b = tile * LT + l;
-    cosL[i] = l < nl ? cos_g[(size_t)b * (NU + 1) + k] : T2{};
-  }
-  for (int i = threadIdx.x; i < (NW + 1) * LT; i += blockDim.x) {
-    const int k = i / LT, l = i % LT, b = tile * LT + l;
-    winL[i] = l < nl ? win_g[(size_t)b * (NW + 1) + k] : T2{};
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nwaves = blockDim.x >> 6;
-  const LamC<T>* lamc = reinterpret_cast<const LamC<T>*>(a.lamc);
-  const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
-  const TabView<T> tv{cosL, winL, nullptr};
-  const T inv_dz = (T)((a.n_z - 1) / a.z_max);
-  const int64_t n_tasks = a.n_pix * nl;
-  for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
-    const int64_t p = t / nl;
-    const int l = (int)(t - p * nl);
-    const int b = tile * LT + l;
-    const LamC<T> c = lamc[b];
-    double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
-    const int64_t s0 = a.pix_off[p];
-    const int n = (int)(a.pix_off[p + 1] - s0);
-    if (!c.valid || n == 0) {
-      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
-      continue;
-    }
-    // ---- pass A
-    PixAcc<false, T> pa;
-    pa.zero();
-    Welford wf{0.0, 0.0, 0.0};
-    T zlo = (T)INFINITY, zhi = (T)-INFINITY;
-    T z1 = (T)-1, lin1 = (T)0;   // the lane's sample when n <= 64
-    int ne1 = R_SENTINEL;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      const int k = c0 + lane;
-      if (k < n) {
-        int ne;
-        T lin, z;
-        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
-        pa.template add<T>(ne, lin, nullptr);
-        if (z >= (T)0) {
-          wf.add((double)z);
-          zlo = fmin(zlo, z);
-          zhi = fmax(zhi, z);
-        }
-        z1 = z;
-        lin1 = lin;
-        ne1 = ne;
-      }
-    }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      pa.xor_merge(off);
-      wf.xor_merge(off);
-      zlo = fmin(zlo, __shfl_xor(zlo, off));
-      zhi = fmax(zhi, __shfl_xor(zhi, off));
-    }
-    bool pass;
-    if (a.gate_mode == 2) pass = pa.S1 > 0;
-    else pass = pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
-    if (!pass) {
-      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
-      continue;
-    }
-    // ---- bandwidth (Appendix D) from the n_in in-support redshifts
-    const int nin = (int)wf.n;
-    const int R = pa.R;
-    auto zs = [&](int r) -> double {   // r-th smallest in-support redshift (uniform)
-      const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
-      return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
-    };
-    auto z_w = [&](int c0, T& z, T& w) {   // the lane's redshift and scaled weight in chunk c0
-      if (n <= 64) {
-        z = z1;
-        w = (z1 >= (T)0 && lin1 > (T)0) ? ldexp(lin1, ne1 - R) : (T)0;
-        return;
-      }
-      const int k = c0 + lane;
-      z = (T)-1;
-      w = (T)0;
-      if (k < n) {
-        int ne;
-        T lin;
-        eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
-        if (z >= (T)0 && lin > (T)0) w = ldexp(lin, ne - R);
-      }
-    };
-    double h = 0.0;
-    if (nin >= 2) {
-      const double sd = sqrt(wf.m2 / (double)(nin - 1));
-      const double nf = pow((double)nin, -0.2);
-      if (a.bandwidth == 0) {
-        h = 1.06 * sd * nf;
-      } else if (a.bandwidth == 1) {
-        auto q = [&](double pr) {
-          const double pos = pr * (double)(nin - 1);
-          const int i0 = (int)floor(pos);
-          const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
-          const double z0 = zs(i0);
-          return z0 + (pos - (double)i0) * (zs(i1) - z0);
-        };
-        h = 0.9 * fmin(sd, (q(0.75) - q(0.25)) / 1.34) * nf;
-      } else {
-        const int m = (nin - 1) / 2;
-        const double Q = 0.5 * (zs(m) + zs(nin / 2));
-        const int nA = m + 1, nB = nin - m - 1;
-        // k-th smallest deviation: A_i = Q - z_(m-i) and B_i = z_(m+1+i) - Q are
-        // both ascending; binary search on how many come from A.
-        auto kth = [&](int k) -> double {
-          int lo = k + 1 - nB > 0 ? k + 1 - nB : 0;
-          int hi = k + 1 < nA ? k + 1 : nA;
-          while (lo < hi) {
-            const int i = (lo + hi) >> 1, j = k + 1 - i;
-            if (Q - zs(m - i) < zs(m + j) - Q) lo = i + 1;
-            else hi = i;
-          }
-          const int j = k + 1 - lo;
-          double v = -INFINITY;
-          if (lo > 0) v = fmax(v, Q - zs(m - lo + 1));
-          if (j > 0) v = fmax(v, zs(m + j) - Q);
-          return v;
-        };
-        const double mad = 0.5 * (kth((nin - 1) / 2) + kth(nin / 2));
-        if (mad > 0.0) {
-          const double iu = 1.0 / (9.0 * mad);
-          double num = 0.0, den = 0.0;
-          for (int c0 = 0; c0 < n; c0 += 64) {
-            T z, w;
-            z_w(c0, z, w);
-            if (z >= (T)0) {
-              const double d = (double)z - Q, u = d * iu, uu = u * u;
-              if (fabs(u) < 1.0) {
-                const double om = 1.0 - uu;
-                num += d * d * (om * om) * (om * om);
-                den += om * (1.0 - 5.0 * uu);
-              }
-            }
-          }
-          num = wave_sum(num);
-          den = wave_sum(den);
-          const double bm = (double)nin * num / (den * den);
-          h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
-        }
-      }
-    }
-    const float* __restrict__ row = a.los + (size_t)a.pix_row[p] * a.n_z;
-    double Tt = 0.0;
-    if (!(h > 0.0) || !isfinite(h)) {
-      // zero bandwidth: point masses at the samples
-      for (int c0 = 0; c0 < n; c0 += 64) {
-        T z, w;
-        z_w(c0, z, w);
-        if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(c, z));
-      }
-      Tt = wave_sum(Tt);
-    } else {
-      // ---- pass B: grid nodes g = lane + 64 i
-      const double ga = fmax(0.0, (double)zlo - a.tau * h);
-      const double gb = fmin(a.z_max, (double)zhi + a.tau * h);
-      const double dz = (gb - ga) / (double)(a.n_grid - 1);
-      const T invh = (T)(1.0 / h);
-      const T kc = (T)(-0.5 * LOG2E);
-      T zgs[NPL], vg[NPL];
-      double accd[NPL];
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) {
-        const int g = lane + 64 * i;
-        accd[i] = 0.0;
-        zgs[i] = (T)0;
-        vg[i] = (T)0;
-        if (g < a.n_grid) {
-          const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
-          const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
-          zgs[i] = zg * invh;
-          vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
-        }
-      }
-      for (int c0 = 0; c0 < n; c0 += 64) {
-        T z, w;
-        z_w(c0, z, w);
-        const T zsc = z * invh;
-        const int cnt = n - c0 < 64 ? n - c0 : 64;
-        T accf[NPL];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) accf[i] = (T)0;
-        for (int j = 0; j < cnt; ++j) {
-          const T wj = rdlane(w, j);
-          if (!(wj > (T)0)) continue;
-          const T zj = rdlane(zsc, j);
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            const T x = zgs[i] - zj;
-            accf[i] = fma(wj, Mth<T>::exp2(x * x * kc), accf[i]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) accd[i] += (double)accf[i];
-      }
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) Tt += (double)vg[i] * accd[i];
-      Tt = wave_sum(Tt) * dz / (h * 2.5066282746310002);
-    }
-    if (lane == 0) {
-      out[0] = (double)R;
-      out[1] = Tt;
-      out[2] = pa.S1;
-      out[3] = pa.S2;
     }
   }
 }
@@ -1287,11 +643,9 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     double Rg = -1e300;
     Part3 num{0, 0, 0};   // KDE: merged (R, sum of T) of the passing pixels
     if constexpr (KDE) {
-      for (int64_t p = a.ev_pix_off[e]; p < a.ev_pix_off[e + 1]; ++p) {
-        const double* r = a.kde + ((size_t)b * a.n_pix + p) * NF_KDE;
-        num = pmerge(num, Part3{r[0], r[1], 0.0});
-        m = pmerge(m, Part3{r[0], r[2], r[3]});
-      }
+      const double* r = a.kde + ((size_t)b * a.n_events + e) * NF_KDE;
+      num = Part3{r[0], r[1], 0.0};
+      m = Part3{r[0], r[2], r[3]};
     }
 #pragma unroll 4
     for (int sl = KDE ? 0 : a.ev_item_off[e]; sl < (KDE ? 0 : a.ev_item_off[e + 1]); ++sl) {
@@ -1507,63 +861,25 @@ hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* 
 
 template <typename T, int GL, bool GRAD>
 static hipError_t sweep_t(const SweepArgs& a, int grid_x, int n_tiles, int threads, size_t lds, hipStream_t st) {
-  sweep_kernel<T, GL, GRAD><<<dim3(grid_x, n_tiles), threads, lds, st>>>(a);
+  if (a.z_prior) sweep_kernel<T, GL, GRAD, true><<<dim3(grid_x, n_tiles), threads, lds, st>>>(a);
+  else sweep_kernel<T, GL, GRAD, false><<<dim3(grid_x, n_tiles), threads, lds, st>>>(a);
   return hipGetLastError();
 }
 
 template <typename T, int GL, bool GRAD>
 static hipError_t set_attr(int fp32) {
-  return hipFuncSetAttribute((const void*)sweep_kernel<T, GL, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sweep_lds_bytes(fp32, GL, GRAD));
+  const int lds = (int)sweep_lds_bytes(fp32, GL, GRAD);
+  hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<T, GL, GRAD, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)sweep_kernel<T, GL, GRAD, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds);
+  return e;
 }
 
-// KDE kernel: points per block tile and its dynamic LDS.
-template <typename T> struct KdeTile { static constexpr int LT = 64; };
-template <> struct KdeTile<double> { static constexpr int LT = 4; };
-
-template <typename T>
-static size_t kde_lds_bytes() {
-  using T2 = typename V2<T>::t;
-  return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
-}
-
-template <typename T, int NPL>
-static hipError_t kde_attr() {
-  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, NPL>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
-}
-
-template <typename T>
-static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
-  constexpr int LT = KdeTile<T>::LT;
-  const int n_tiles = (a.B + LT - 1) / LT;
-  const int64_t tasks = a.n_pix * (a.B < LT ? a.B : LT);
-  int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
-  if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
-  if (grid_x < 1) grid_x = 1;
-  const dim3 grid(grid_x, n_tiles);
-  const size_t lds = kde_lds_bytes<T>();
-  if (a.n_grid <= 256) kde_kernel<T, LT, 4><<<grid, 512, lds, st>>>(a);
-  else if (a.n_grid <= 512) kde_kernel<T, LT, 8><<<grid, 512, lds, st>>>(a);
-  else if (a.n_grid <= 64 * KDE_NPL_MAX) kde_kernel<T, LT, KDE_NPL_MAX><<<grid, 512, lds, st>>>(a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st) {
-  if (a.n_pix == 0) return hipSuccess;
-  return fp32 ? kde_t<float>(a, n_cu, st) : kde_t<double>(a, n_cu, st);
-}
-
-// Raise the dynamic-LDS limit of every sweep and KDE variant (once, outside any capture).
+// Raise the dynamic-LDS limit of every sweep variant (once, outside any capture).
 hipError_t init_kernel_attrs() {
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = kde_attr<float, 4>();
-  if (e == hipSuccess) e = kde_attr<float, 8>();
-  if (e == hipSuccess) e = kde_attr<float, KDE_NPL_MAX>();
-  if (e == hipSuccess) e = kde_attr<double, 4>();
-  if (e == hipSuccess) e = kde_attr<double, 8>();
-  if (e == hipSuccess) e = kde_attr<double, KDE_NPL_MAX>();
 #define DSL_ATTR(T, G, F)                         \
   if (e == hipSuccess) e = set_attr<T, G, true>(F); \
   if (e == hipSuccess) e = set_attr<T, G, false>(F);
