@@ -16,40 +16,52 @@ namespace dsl {
 __device__ __forceinline__ float rdlane(float x, int j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
+__device__ __forceinline__ int rdlane(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 __device__ __forceinline__ double rdlane(double x, int j) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
-  return x;
+// Cross-lane moves inside the DPP row patterns of gfx9: lane i of the result
+// takes x from the lane the control selects; rows outside ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp32<CTRL, ROWS>((int)(b & 0xffffffff));
+  const int hi = dpp32<CTRL, ROWS>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(dpp32<CTRL, ROWS>(__float_as_int(x)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp(int x) {
+  return dpp32<CTRL, ROWS>(x);
 }
 
-// Running mean and sum of squared deviations; the merge is symmetric in its
-// operands (so a butterfly leaves every lane with the same bits) and keeps an
-// exact zero spread for equal values.
-struct Welford {
-  double n, mean, m2;
-  __device__ __forceinline__ void add(double x) {
-    n += 1.0;
-    const double d = x - mean;
-    mean += d / n;
-    m2 += d * (x - mean);
-  }
-  __device__ __forceinline__ void xor_merge(int off) {
-    const double on = __shfl_xor(n, off), om = __shfl_xor(mean, off), o2 = __shfl_xor(m2, off);
-    const double nt = n + on;
-    if (nt == 0.0) return;
-    const double d = om - mean;
-    const double mm = (d == 0.0) ? mean : (n * mean + on * om) / nt;
-    m2 = (m2 + o2) + d * d * (n * on / nt);
-    mean = mm;
-    n = nt;
-  }
-};
+// Reduction over the 64 lanes of a wavefront (every lane active), returned to
+// all lanes: pairs and quads (quad_perm), half rows (row_half_mirror), rows
+// (row_mirror), then rows 0+1 and 2+3 (row_bcast:15) and all four rows
+// (row_bcast:31), read from lane 63.  The order is fixed, so it is deterministic.
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_reduce(V x, Op op) {
+  x = op(x, dpp<0xB1, 0xf>(x));    // quad_perm [1,0,3,2]
+  x = op(x, dpp<0x4E, 0xf>(x));    // quad_perm [2,3,0,1]
+  x = op(x, dpp<0x141, 0xf>(x));   // row_half_mirror
+  x = op(x, dpp<0x140, 0xf>(x));   // row_mirror
+  x = op(x, dpp<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+  x = op(x, dpp<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3
+  return rdlane(x, 63);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  return wave_reduce(x, [](double a, double b) { return a + b; });
+}
 
 // Linear interpolation of a redshift-prior row at z in [0, z_max].
 template <typename T>
@@ -122,19 +134,22 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
     // ---- pass A
     PixAcc<false, T> pa;
     pa.zero();
-    Welford wf{0.0, 0.0, 0.0};
+    double sz = 0.0, szz = 0.0;   // in-support redshift moments
     T zlo = (T)INFINITY, zhi = (T)-INFINITY;
+    int nin = 0;
     T z1 = (T)-1, lin1 = (T)0;   // the lane's sample when n <= 64
     int ne1 = R_SENTINEL;
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int k = c0 + lane;
+      T z = (T)-1;
       if (k < n) {
         int ne;
-        T lin, z;
+        T lin;
         eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
         pa.template add<T>(ne, lin, nullptr);
         if (z >= (T)0) {
-          wf.add((double)z);
+          sz += (double)z;
+          szz += (double)z * (double)z;
           zlo = fmin(zlo, z);
           zhi = fmax(zhi, z);
         }
@@ -142,24 +157,23 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
         lin1 = lin;
         ne1 = ne;
       }
+      nin += (int)__popcll(__ballot(z >= (T)0));
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      pa.xor_merge(off);
-      wf.xor_merge(off);
-      zlo = fmin(zlo, __shfl_xor(zlo, off));
-      zhi = fmax(zhi, __shfl_xor(zhi, off));
-    }
+    const int R = wave_reduce(pa.R, [](int x, int y) { return x > y ? x : y; });
+    const double S1 = wave_sum(ldexp(pa.S1, pa.R - R));
+    const double S2 = wave_sum(ldexp(pa.S2, 2 * (pa.R - R)));
     bool pass;
-    if (a.gate_mode == 2) pass = pa.S1 > 0;
-    else pass = pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
+    if (a.gate_mode == 2) pass = S1 > 0;
+    else pass = S2 > 0 && S1 * S1 >= a.neff_min * S2;
     if (!pass) {
       if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
       continue;
     }
+    sz = wave_sum(sz);
+    szz = wave_sum(szz);
+    zlo = wave_reduce(zlo, [](T x, T y) { return fmin(x, y); });
+    zhi = wave_reduce(zhi, [](T x, T y) { return fmax(x, y); });
     // ---- bandwidth (Appendix D) from the n_in in-support redshifts
-    const int nin = (int)wf.n;
-    const int R = pa.R;
     auto zs = [&](int r) -> double {   // r-th smallest in-support redshift (uniform)
       const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
       return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
@@ -181,8 +195,8 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
       }
     };
     double h = 0.0;
-    if (nin >= 2) {
-      const double sd = sqrt(wf.m2 / (double)(nin - 1));
+    if (nin >= 2 && zlo < zhi) {   // equal redshifts: zero spread, zero bandwidth
+      const double sd = sqrt(fmax(szz - sz * sz / (double)nin, 0.0) / (double)(nin - 1));
       const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));   // n^(-1/5)
       if (a.bandwidth == 0) {
         h = 1.06 * sd * nf;
@@ -299,8 +313,8 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
     if (lane == 0) {
       out[0] = (double)R;
       out[1] = Tt;
-      out[2] = pa.S1;
-      out[3] = pa.S2;
+      out[2] = S1;
+      out[3] = S2;
     }
   }
   if (a.evals && lane == 0 && evals) atomicAdd(a.evals, evals);
