@@ -24,7 +24,9 @@ sys.path.insert(0, ROOT)
 # Algorithmic work per sample-weight (one sample or injection, one Lambda):
 # floating-point operations of the weight formula as the sweep evaluates it
 # (add/mul = 1, fused multiply-add = 2, each exp2/log2/rcp/rsqrt/sqrt = 1),
-# counted from the source; see the design doc for the breakdown.
+# counted from the source: the forward weight (distance inversion, frame
+# change, Jacobian, prior, rate, mixture, window, smoothing, exponent
+# bookkeeping) and, for the adjoint, its 16 basis derivatives and sums.
 FLOP_PER_WEIGHT_FWD = 175
 FLOP_PER_WEIGHT_GRAD = 360
 # KDE numerator: the weight without prior and rate (164), and per (sample, grid

@@ -27,7 +27,7 @@ What is computed (paper, Sec. II A "Hierarchical Likelihood"):
 * Eq. (3) with the scale-free rate prior of Sec. II A:
   ln L = sum_i ln L_i - N_det ln alpha.
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 * MultiPeak (power law + two Gaussian peaks + low-mass smoothing, cited in
   Appendix A): p1(m1) = S(m1) [(1-lg) P(m1) + lg ll N_T(m1; mu_l, s_l)
   + lg (1-ll) N_T(m1; mu_h, s_h)] on [mmin, mmax]; P the normalised power law

@@ -49,8 +49,8 @@ LAMBDA_NAMES = (
 N_LAMBDA = len(LAMBDA_NAMES)
 IDX = {n: i for i, n in enumerate(LAMBDA_NAMES)}
 
-# Population values of the paper's Table II; cosmology of the BASELINE point
-# (H0 = 70, Omega_m = 0.3) instead of Table II's Planck values.
+# Population values of the paper's Table II; the fiducial cosmology is
+# H0 = 70, Omega_m = 0.3 (the benchmark point) instead of Table II's Planck values.
 TABLE_II = dict(alpha=2.9, beta=1.0, mmin=4.6, mmax=86.3, delta_m=4.8,
                 mu_low=9.7, sigma_low=0.7, mu_high=30.7, sigma_high=6.3,
                 lambda_g=0.4, lambda_low=0.8, gamma=3.3, kappa=2.9, z_p=2.5)

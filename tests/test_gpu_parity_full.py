@@ -123,6 +123,34 @@ def test_config4_o5_like_sampled(mods):
     lik.close()
 
 
+def test_config4_kde_sampled(mods):
+    """O5-like catalogue at full size with the KDE numerator in the benchmark's
+    KDE launch (64 points, Scott bandwidth, 256-node grid): sampled events and
+    points against the oracle's loglike_kde."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    log("[c4 full KDE: generate]")
+    cat = synth.make_catalog("c4")
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision="fp32", numerator="kde")
+    lam = synth.lambdas_for("c4")
+    r = lik.loglike(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    ev = r["logL_event"].cpu().numpy()
+    ne = r["neff_event"].cpu().numpy()
+    log(f"  finite ln L: {int(np.isfinite(r['logL'].cpu().numpy()).sum())} / 64")
+    rng = np.random.default_rng(9)
+    events = np.sort(rng.choice(cat.n_events, 4, replace=False))
+    events = np.unique(np.append(events, int(np.argmax(cat.samples_per_event()))))
+    sub = cat.subset(events, inj=slice(0, 1000))
+    n_amb = 0
+    for b in [0, 40, 63]:
+        ref = O.loglike_kde(sub, lam[b], margins=True)
+        refc = dict(logL_event=ref["logL_event"], neff_event=ref["neff_event"],
+                    gate_margin=ref["gate_margin"], sample_margin=ref["sample_margin"])
+        n_amb += check_events(ev[b, events], ne[b, events], refc, TOL_LOGL_FP32)
+    log(f"  sampled events {events.tolist()} ok, ambiguous {n_amb}")
+    lik.close()
+
+
 def test_config5_gradient(mods):
     """Adjoint on the config-1 catalogue (64 points per launch) and on a 50-event
     subset of config 2, against the oracle's autograd gradient."""
