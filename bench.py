@@ -9,7 +9,8 @@ and d ln L / d Lambda (all 16 entries) in one call of dsl_loglike_grad.
 Prints one JSON line.  `value` = Lambda-evaluations (ln L + gradient) per
 second; the roofline object reports the dominant kernel (the fused weight +
 adjoint sweep) against the FP32 vector peak; cpu_baseline is the FP64 oracle
-on a bounded sample of the same workload.
+on a bounded sample of the same workload.  `kde_numerator` times the same
+points with the paper's KDE numerator (value only) on the same handle.
 """
 import argparse
 import json
@@ -59,6 +60,9 @@ def parse():
     p.add_argument("--numerator", default="mc", choices=["mc", "kde"],
                    help="mc: per-sample sums (default); kde: the paper's KDE form (value only)")
     p.add_argument("--kde-bandwidth", default="scott", choices=["scott", "silverman", "biweight"])
+    p.add_argument("--kde-steps", type=int, default=3,
+                   help="after the main timing on c4, time this many steps of the same points with the KDE "
+                        "numerator on the same handle (0: skip); reported under 'kde_numerator'")
     p.add_argument("--copy-calib", type=int, default=0,
                    help="after the timed steps, run one elementwise copy of this many MiB (calibrates "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -159,11 +163,26 @@ def main():
     torch.cuda.synchronize()
     print("# warm-up done", file=sys.stderr, flush=True)
 
-    # timed region: K steps, HIP events around each kernel on the launch stream
-    lik.set_option("timing", 1)
-    sweep_ms, setup_ms, comb_ms, pix_ms = [], [], [], []
+    # timed region: K steps as the library runs them (captured HIP graphs, no host
+    # synchronisation between steps), bracketed by a device synchronisation
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step(st)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = B * args.steps / wall
+    ms_per_step_events = ev0.elapsed_time(ev1) / args.steps
+
+    # kernel durations: the same K steps again with HIP events recorded around
+    # each kernel on the launch stream (option "timing"; launches not captured)
+    lik.set_option("timing", 1)
+    sweep_ms, setup_ms, comb_ms, pix_ms = [], [], [], []
     for _ in range(args.steps):
         step(st)
         a, b, c = lik.timing()
@@ -173,10 +192,7 @@ def main():
         if kde:
             pix_ms.append(lik.info("ms_pixels"))
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     lik.set_option("timing", 0)
-    ms_per_step = 1e3 * wall / args.steps
-    value = B * args.steps / wall
     n_w = cat.n_samp + cat.n_inj
     flags_h = flags.cpu().numpy()
     finite = int(np.isfinite(logL.cpu().numpy()).sum())
@@ -249,6 +265,49 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the paper's KDE numerator on the same catalogue and points (value only)
+    kde_side = None
+    if args.kde_steps > 0 and args.config == "c4" and not kde:
+        lik.set_option("numerator", 1)
+        lik.set_option("kde_bandwidth", {"scott": 0, "silverman": 1, "biweight": 2}[args.kde_bandwidth])
+        out = torch.empty(B, dtype=torch.float64, device=dev)
+
+        def kstep():
+            rc = lib.dsl_loglike(lik.h, C.c_void_p(lam.data_ptr()), B, C.c_void_p(out.data_ptr()), None, None,
+                                 None, None, C.c_void_p(st))
+            if rc:
+                raise RuntimeError(lib.dsl_last_error().decode())
+        kstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.kde_steps):
+            kstep()
+        torch.cuda.synchronize()
+        kwall = time.perf_counter() - t1
+        lik.set_option("timing", 1)
+        kms = []
+        for _ in range(args.kde_steps):
+            kstep()
+            lik.timing()
+            kms.append(lik.info("ms_pixels"))
+        torch.cuda.synchronize()
+        lik.set_option("timing", 0)
+        kev = lik.info("kde_evals")
+        kavg = float(np.mean(kms))
+        kfl = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kev
+        kach = kfl / (kavg * 1e-3) / 1e12
+        kde_side = {"metric": "Lambda-evaluations/sec (log L, KDE numerator (%s), %d-node grid)"
+                              % (args.kde_bandwidth, int(lik.info("kde_grid"))),
+                    "value": round(B * args.kde_steps / kwall, 3), "unit": "Lambda-evals/s",
+                    "steps": args.kde_steps, "ms_per_step": round(1e3 * kwall / args.kde_steps, 3),
+                    "finite_logL": int(np.isfinite(out.cpu().numpy()).sum()),
+                    "roofline": {"bound": "alu", "achieved": round(kach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(kach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                                 "traffic": None, "kernel": "kde_kernel<float,64,4> + kde_event_kernel",
+                                 "kernel_ms": round(kavg, 3), "kde_node_evals_per_launch": kev,
+                                 "flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE}}
+        lik.set_option("numerator", 0)
+
     cpu = None
     if not args.no_cpu_baseline and args.config in ("c4", "c2"):
         cpu = cpu_baseline(cat, lam_np[0], grad, args.kde_bandwidth if kde else None)
@@ -258,7 +317,8 @@ def main():
         "metric": ("Lambda-evaluations/sec (%s) on O5-like catalogue" % what) if args.config == "c4"
         else "Lambda-evaluations/sec (%s), workload %s" % (what, args.config),
         "value": round(value, 3), "unit": "Lambda-evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_hip_events": round(ms_per_step_events, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %d events, %d samples, %d pixels x %d-node LOS tables (%.2f GB), %d injections, "
@@ -270,12 +330,15 @@ def main():
                                   % (args.kde_bandwidth, int(lik.info("kde_grid"))) if kde else "ln L"),
                    "B": B, "precision": "FP32 weights, FP64 sums" if precision == "fp32" else "FP64"},
         "gsample_weights_per_s": round(n_w * B * args.steps / wall / 1e9, 3),
+        "kernel_timing": "HIP events around each kernel on the launch stream, a second pass of K steps",
         "kernel_ms": {"setup": round(float(np.mean(setup_ms)), 4), "sweep": round(sweep_avg, 4),
                       "combine": round(float(np.mean(comb_ms)), 4),
                       **({"kde": round(kde_avg, 4)} if kde else {})},
         "finite_logL": finite, "flags_nonzero": int((flags_h != 0).sum()),
         "roofline": roofline, "cpu_baseline": cpu, "single_lambda_launches": single,
     }
+    if kde_side:
+        res["kde_numerator"] = kde_side
     print(json.dumps(res), flush=True)
     lik.close()
 

@@ -115,7 +115,7 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals, cpart;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -280,12 +280,13 @@ int pack_samples(dsl_handle* h, DevBuf& out, const double* m1, const double* m2,
 // Target samples per work item: about 16 items per CU for one-point tiles
 // (a wavefront then sweeps 64 samples per step), 64 per CU otherwise.
 // Default work-item size: about 256 items per compute unit for batched tiles
-// (what the autotuner picks on the 33M-weight catalogue), 16 for one point.
+// and 64 for one-point tiles (what the autotuner picks on the 33M- and
+// 3.6M-weight catalogues), at least 64 samples.
 int64_t auto_chunk(const dsl_handle* h, int GL) {
   const int64_t total = h->n_samp + h->n_inj;
-  const int64_t per_cu = GL == 1 ? 16 : 256;
+  const int64_t per_cu = GL == 1 ? 64 : 256;
   int64_t c = total / ((int64_t)h->n_cu * per_cu);
-  return std::max<int64_t>(GL == 1 ? 256 : 64, std::min<int64_t>(16384, c));
+  return std::max<int64_t>(64, std::min<int64_t>(16384, c));
 }
 
 // Work list: runs of whole pixels of one event (about `chunk` samples each; a
@@ -392,6 +393,14 @@ SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   return c;
 }
 
+// Combine workgroups per point: about one per 256 work items, at most 32, and
+// no more than 8 per compute unit over the batch.
+int combine_slices(const dsl_handle* h, int B) {
+  const int by_items = (h->n_items + 255) / 256;
+  const int by_cu = (8 * h->n_cu + B - 1) / B;
+  return std::max(1, std::min(32, std::min(by_items, by_cu)));
+}
+
 int ensure_workspace(dsl_handle* h, int B, bool grad) {
   const int NU = h->fp32 ? NU_F32 : NU_F64, NW = h->fp32 ? NW_F32 : NW_F64;
   const size_t t1 = h->fp32 ? sizeof(float) : sizeof(double);
@@ -410,6 +419,8 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
   if (h->numerator == 1 &&
       (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_pix, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
+  if ((e = h->cpart.ensure(sizeof(double) * NF_CSLICE * (size_t)B * combine_slices(h, B))) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (combine slices)");
   if (h->numerator == 1 && (e = h->kde_evals.ensure(sizeof(unsigned long long))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE counter)");
   if (h->numerator == 1 &&
@@ -522,6 +533,8 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.grad = o.grad;
   c.gmap = h->gmap.as<double>();
   c.kde = h->numerator == 1 ? h->kde_ev.as<double>() : nullptr;
+  c.n_slices = combine_slices(h, B);
+  c.cpart = h->cpart.as<double>();
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -835,7 +848,11 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
   for (int gl : gls) {
     if (gl > 1 && B < gl / 4) continue;   // mostly idle lanes
     const int64_t base = auto_chunk(h, gl);
-    const std::vector<int64_t> chunks = {std::max<int64_t>(64, base / 4), base, std::min<int64_t>(65536, base * 4)};
+    std::vector<int64_t> chunks;
+    for (int64_t ch : {base / 16, base / 4, base, base * 4}) {
+      ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
+      if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
+    }
     for (int64_t ch : chunks) {
       SweepCfg c;
       c.GL = gl;

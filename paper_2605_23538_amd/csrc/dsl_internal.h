@@ -156,6 +156,10 @@ struct GateSplitArgs {
   int32_t gate_mode;
 };
 
+// Combine slice record: sum of ln L_i, events used, flags, selection (R, S1,
+// S2), 16 event basis sums, 16 selection basis sums.
+constexpr int NF_CSLICE = 38;
+
 struct CombineArgs {
   const double* part;        // [B][n_items][nf]
   int32_t n_items;
@@ -177,6 +181,8 @@ struct CombineArgs {
   double* grad;                 // [B][16] or null
   const double* gmap;           // [B][N_GMAP] (adjoint only)
   const double* kde;            // [B][n_events][NF_KDE] event records (KDE numerator) or null
+  int32_t n_slices;             // workgroups per point (events and injection slots strided over them)
+  double* cpart;                // [B][n_slices][NF_CSLICE] slice records when n_slices > 1
 };
 
 }  // namespace dsl

@@ -1,6 +1,6 @@
 // HIP kernels (gfx950) of the dark-siren population log-likelihood.
 //
-//   setup_kernel    one workgroup per hyperparameter point: FP64 cosmology and
+//   setup_kernel    two workgroups per hyperparameter point: FP64 cosmology and
 //                   mass-model constants, the z(d_L) inverse table and the
 //                   smoothing-window tables (Eq. 1 and the MultiPeak model).
 //   sweep_kernel    persistent sweep over work items (runs of whole pixels of
@@ -94,73 +94,107 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   const double M = mmin + dm;
   const double s = beta + 1.0;
 
-  // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
-  constexpr int KZ = 256;
-  __shared__ double Itab[KZ + 1];
-  const double hz = z_max / KZ;
-  for (int k = tid; k < KZ; k += blockDim.x) {
-    double sacc = 0.0;
-    if (ok) {
-      const double c = (k + 0.5) * hz;
-      for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(c + 0.5 * hz * GL8_X[q], Om);
-      sacc *= 0.5 * hz;
-    }
-    Itab[k + 1] = sacc;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    Itab[0] = 0.0;
-    for (int k = 1; k <= KZ; ++k) Itab[k] += Itab[k - 1];
-  }
-  __syncthreads();
-  // I(z) = Itab[k] + 8-point Gauss-Legendre over [z_k, z]
-  auto I_at = [&](double z) {
-    int k = (int)(z / hz);
-    k = k < 0 ? 0 : (k > KZ - 1 ? KZ - 1 : k);
-    const double a = k * hz, h = z - a;
-    double sacc = 0.0;
-    for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(a + 0.5 * h * (GL8_X[q] + 1.0), Om);
-    return Itab[k] + 0.5 * h * sacc;
-  };
-  // --- inverse distance table: y(v) = z/u at v_k = 1 + k h_v, u = (v^2-1)/4.
-  const double umax = ok ? (1.0 + z_max) * Itab[KZ] : 1.0;
-  const double vmax = sqrt(1.0 + 4.0 * umax);
-  const double hv = (vmax - 1.0) / NU;
-  for (int k = tid; k <= NU; k += blockDim.x) {
-    double y = 1.0, dy = -(1.0 - 0.75 * Om) * 0.5;  // limits at u = 0
-    if (k > 0 && ok) {
-      const double dv = k * hv;
-      const double u = dv * (2.0 + dv) * 0.25;
-      const double v = 1.0 + dv;
-      // bracket: the panel [z_j, z_j+1] with D(z_j) <= u <= D(z_j+1), D = (1+z) I
-      int lo = 0, hi = KZ;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((1.0 + mid * hz) * Itab[mid] <= u) lo = mid; else hi = mid;
+  // two workgroups per point: part 0 the cosmology and rate, part 1 the mass model
+  const int part = blockIdx.y;
+  LamC<T>& c = lamc[b];
+  if (part == 0) {
+    // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
+    constexpr int KZ = 256;
+    __shared__ double Itab[KZ + 1];
+    const double hz = z_max / KZ;
+    for (int k = tid; k < KZ; k += blockDim.x) {
+      double sacc = 0.0;
+      if (ok) {
+        const double c = (k + 0.5) * hz;
+        for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(c + 0.5 * hz * GL8_X[q], Om);
+        sacc *= 0.5 * hz;
       }
-      const double za = lo * hz, zb = hi * hz;
-      const double Da = (1.0 + za) * Itab[lo], Db = (1.0 + zb) * Itab[hi];
-      double z = za + (zb - za) * (u - Da) / (Db - Da);
-      for (int it = 0; it < 12; ++it) {
+      Itab[k + 1] = sacc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Itab[0] = 0.0;
+      for (int k = 1; k <= KZ; ++k) Itab[k] += Itab[k - 1];
+    }
+    __syncthreads();
+    // I(z) = Itab[k] + 8-point Gauss-Legendre over [z_k, z]
+    auto I_at = [&](double z) {
+      int k = (int)(z / hz);
+      k = k < 0 ? 0 : (k > KZ - 1 ? KZ - 1 : k);
+      const double a = k * hz, h = z - a;
+      double sacc = 0.0;
+      for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(a + 0.5 * h * (GL8_X[q] + 1.0), Om);
+      return Itab[k] + 0.5 * h * sacc;
+    };
+    // --- inverse distance table: y(v) = z/u at v_k = 1 + k h_v, u = (v^2-1)/4.
+    const double umax = ok ? (1.0 + z_max) * Itab[KZ] : 1.0;
+    const double vmax = sqrt(1.0 + 4.0 * umax);
+    const double hv = (vmax - 1.0) / NU;
+    for (int k = tid; k <= NU; k += blockDim.x) {
+      double y = 1.0, dy = -(1.0 - 0.75 * Om) * 0.5;  // limits at u = 0
+      if (k > 0 && ok) {
+        const double dv = k * hv;
+        const double u = dv * (2.0 + dv) * 0.25;
+        const double v = 1.0 + dv;
+        // bracket: the panel [z_j, z_j+1] with D(z_j) <= u <= D(z_j+1), D = (1+z) I
+        int lo = 0, hi = KZ;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if ((1.0 + mid * hz) * Itab[mid] <= u) lo = mid; else hi = mid;
+        }
+        const double za = lo * hz, zb = hi * hz;
+        const double Da = (1.0 + za) * Itab[lo], Db = (1.0 + zb) * Itab[hi];
+        double z = za + (zb - za) * (u - Da) / (Db - Da);
+        for (int it = 0; it < 12; ++it) {
+          const double I = I_at(z);
+          const double f = (1.0 + z) * I - u;
+          double zn = z - f / (I + (1.0 + z) / E_of(z, Om));
+          zn = fmin(fmax(zn, za), zb);
+          const bool done = fabs(zn - z) <= 4e-16 * zn;
+          z = zn;
+          if (done) break;
+        }
         const double I = I_at(z);
-        const double f = (1.0 + z) * I - u;
-        double zn = z - f / (I + (1.0 + z) / E_of(z, Om));
-        zn = fmin(fmax(zn, za), zb);
-        const bool done = fabs(zn - z) <= 4e-16 * zn;
-        z = zn;
-        if (done) break;
+        const double zp_u = 1.0 / (I + (1.0 + z) / E_of(z, Om));
+        y = z / u;
+        dy = (zp_u * u - z) / (u * u) * (0.5 * v);
       }
-      const double I = I_at(z);
-      const double zp_u = 1.0 / (I + (1.0 + z) / E_of(z, Om));
-      y = z / u;
-      dy = (zp_u * u - z) / (u * u) * (0.5 * v);
+      T2 e;
+      e.x = (T)y;
+      e.y = (T)(dy * hv);
+      cos_tab[(size_t)b * (NU + 1) + k] = e;
     }
-    T2 e;
-    e.x = (T)y;
-    e.y = (T)(dy * hv);
-    cos_tab[(size_t)b * (NU + 1) + k] = e;
-  }
 
+    if (tid == 0) {
+      c.H0 = (T)H0;
+      c.u_max = (T)umax;
+      c.inv_hv = (T)(1.0 / hv);
+      c.Om = (T)Om;
+      c.OL = (T)(1.0 - Om);
+      c.c0 = (T)log2(H0 / C_KMS);
+      c.gm3 = (T)(gam - 3.0);
+      c.gk = (T)(gam + kap);
+      c.Lp = (T)log2(1.0 + zp);
+      c.gamma = (T)gam;
+      c.kappa = (T)kap;
+      c.inv_opzp = (T)(1.0 / (1.0 + zp));
+      c.inv_H0 = (T)(1.0 / H0);
+      c.om_case = Om < 1e-6 ? 1 : (Om > 1 - 1e-6 ? 2 : 0);
+      c.k23 = c.om_case == 0 ? (T)((2.0 / 3.0) / (1.0 - Om)) : (T)0;
+      c.hOm = c.om_case == 0 ? (T)(0.5 / Om) : (T)0;
+      c.valid = ok ? 1 : 0;
+      valid_out[b] = ok ? 1 : 0;
+      if (gmap) {
+        double* gm = gmap + (size_t)b * N_GMAP;
+        gm[0] = 1.0 / H0;
+        gm[20] = (gam + kap) / (1.0 + zp);
+        gm[21] = LN2;
+        gm[22] = 0.0;
+        gm[23] = 0.0;
+      }
+    }
+    return;
+  }
   // --- smoothing-window integrals on NW panels (Gauss-Legendre 8 x 2 per panel)
   // panel integrals of m^beta S, and of m^beta d S/d(beta, m_min, dm) for the adjoint.
   const bool win = ok && dm > 0;
@@ -250,7 +284,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   }
 
   if (tid == 0) {
-    LamC<T> c;
     const double r2pi = 2.5066282746310002;
     double lnbP, dbPa, dbPmin, dbPmax;
     if (fabs(alpha - 1.0) < 1e-10) {
@@ -284,12 +317,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     dnorm(muL, sL, dLmu, dLsg, dLlo, dLhi);
     dnorm(muH, sH, dHmu, dHsg, dHlo, dHhi);
     const double l2 = LOG2E;
-    c.H0 = (T)H0;
-    c.u_max = (T)umax;
-    c.inv_hv = (T)(1.0 / hv);
-    c.Om = (T)Om;
-    c.OL = (T)(1.0 - Om);
-    c.c0 = (T)log2(H0 / C_KMS);
     c.alpha = (T)alpha;
     c.beta = (T)beta;
     c.mmin = (T)mmin;
@@ -307,9 +334,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     c.inv_s = (T)(1.0 / s);
     c.lM = (T)log2(M);
     c.zw = (T)zw_s[0];
-    c.gm3 = (T)(gam - 3.0);
-    c.gk = (T)(gam + kap);
-    c.Lp = (T)log2(1.0 + zp);
     c.dbP_alpha = (T)dbPa;
     c.dbP_mmin = (T)dbPmin;
     c.dbP_mmax = (T)dbPmax;
@@ -328,13 +352,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     c.zw_beta = (T)zw_s[1];
     c.zw_mmin = (T)zw_s[2];
     c.zw_dm = (T)zw_s[3];
-    c.gamma = (T)gam;
-    c.kappa = (T)kap;
-    c.inv_opzp = (T)(1.0 / (1.0 + zp));
-    c.inv_H0 = (T)(1.0 / H0);
-    c.om_case = Om < 1e-6 ? 1 : (Om > 1 - 1e-6 ? 2 : 0);
-    c.k23 = c.om_case == 0 ? (T)((2.0 / 3.0) / (1.0 - Om)) : (T)0;
-    c.hOm = c.om_case == 0 ? (T)(0.5 / Om) : (T)0;
     c.isL2 = (T)(1.0 / (sL * sL));
     c.isL3 = (T)(1.0 / (sL * sL * sL));
     c.isH2 = (T)(1.0 / (sH * sH));
@@ -344,12 +361,8 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     c.aLl = ll > 0 ? (T)(1.0 / ll) : (T)0;
     c.aHl = ll < 1 ? (T)(1.0 / (1.0 - ll)) : (T)0;
     c.inv_s2 = (T)(1.0 / (s * s));
-    c.valid = ok ? 1 : 0;
-    lamc[b] = c;
-    valid_out[b] = c.valid;
     if (gmap) {
       double* gm = gmap + (size_t)b * N_GMAP;
-      gm[0] = 1.0 / H0;
       gm[1] = dbPa;
       gm[2] = dbPmin;
       gm[3] = dLlo;
@@ -369,10 +382,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
       gm[17] = lg > 0 ? 1.0 / lg : 0.0;
       gm[18] = ll > 0 ? 1.0 / ll : 0.0;
       gm[19] = ll < 1 ? 1.0 / (1.0 - ll) : 0.0;
-      gm[20] = (gam + kap) / (1.0 + zp);
-      gm[21] = LN2;
-      gm[22] = 0.0;
-      gm[23] = 0.0;
     }
   }
 }
@@ -427,12 +436,19 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
                                           T* g) {
   constexpr int NS = 64 / GL;
   if (s1 <= s0) return;
-  Samp<T> nxt = ld_samp<T, NS>(base, s0 + sg < s1 ? s0 + sg : s1 - 1);
+  // indices are clamped into the run; with several samples per wavefront two
+  // records are in flight (one point per lane leaves little work to hide a load)
+  auto at = [&](int64_t sb) { const int64_t i = sb + sg; return i < s1 ? i : s1 - 1; };
+  Samp<T> nxt = ld_samp<T, NS>(base, at(s0));
+  Samp<T> nxt2;
+  if constexpr (NS > 1) nxt2 = ld_samp<T, NS>(base, at(s0 + NS));
   for (int64_t sb = s0; sb < s1; sb += NS) {
     const Samp<T> cur = nxt;
-    if (sb + NS < s1) {
-      const int64_t ni = sb + NS + sg;
-      nxt = ld_samp<T, NS>(base, ni < s1 ? ni : s1 - 1);
+    if constexpr (NS > 1) {
+      nxt = nxt2;
+      if (sb + 2 * NS < s1) nxt2 = ld_samp<T, NS>(base, at(sb + 2 * NS));
+    } else if (sb + NS < s1) {
+      nxt = ld_samp<T, NS>(base, at(sb + NS));
     }
     if (sb + sg < s1 && live) {
       int n;
@@ -616,6 +632,61 @@ __device__ inline Part3 pmerge(Part3 x, Part3 y) {
   return r;
 }
 
+// ln L, N_eff of the selection term, flags and the gradient map of one point
+// from its merged sums (redg / gsel: 16 values with strides rs / gs).
+template <bool GRAD>
+__device__ void combine_finish(const CombineArgs& a, int b, double acc, double nused, unsigned int flags,
+                               const double* redg, int rs, Part3 sel, const double* gsel, int gs) {
+  const double ln2 = LN2;
+  const bool valid = a.valid[b] != 0;
+  {
+    const Part3 s = sel;
+    unsigned int f = flags;
+    double logL = -INFINITY;
+    double lna = -INFINITY;
+    if (!valid) f |= 1u;
+    if (valid && s.S1 > 0) lna = log(s.S1) + s.R * ln2 - a.ln_ndraw;
+    else if (valid) f |= 4u;
+    if (f == 0) {
+      logL = acc - (double)a.n_events * lna;
+      if (!isfinite(logL)) {
+        f |= 8u;
+        logL = -INFINITY;
+      }
+    }
+    a.logL[b] = logL;
+    if (a.neff_sel) a.neff_sel[b] = s.S1 > 0 ? s.S1 * s.S1 / s.S2 : 0.0;
+    if (a.flags) a.flags[b] = f;
+    if constexpr (GRAD) {
+      if (a.grad) {
+        // basis totals T_j = sum_i B_ij / S1_i - N_det B_sel,j / S1_sel, then the map
+        double T[16];
+        for (int p = 0; p < 16; ++p) T[p] = (f == 0) ? redg[p * rs] - (double)a.n_events * gsel[p * gs] / s.S1 : 0.0;
+        const double* c = a.gmap + (size_t)b * N_GMAP;
+        const double T1 = nused - (double)a.n_events;   // coefficient of the constant 1/H0 term
+        double g[16];
+        g[0] = c[0] * T1 + T[0];
+        g[1] = T[1];
+        g[2] = c[1] * T[2] - T[3];
+        g[3] = T[4];
+        g[4] = c[2] * T[2] + c[3] * T[5] + c[4] * T[6] - T[7];
+        g[5] = c[5] * T[2] + c[6] * T[5] + c[7] * T[6];
+        g[6] = T[8];
+        g[7] = c[8] * T[5] + c[12] * T[9];
+        g[8] = c[9] * T[5] + c[13] * T[10];
+        g[9] = c[10] * T[6] + c[14] * T[11];
+        g[10] = c[11] * T[6] + c[15] * T[12];
+        g[11] = -c[16] * T[2] + c[17] * (T[5] + T[6]);
+        g[12] = c[18] * T[5] - c[19] * T[6];
+        g[13] = c[21] * T[13] - T[14];
+        g[14] = -T[14];
+        g[15] = c[20] * T[15];
+        for (int p = 0; p < 16; ++p) a.grad[(size_t)b * 16 + p] = (f == 0) ? g[p] : 0.0;
+      }
+    }
+  }
+}
+
 template <bool GRAD, bool KDE = false>
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   static_assert(!(GRAD && KDE), "the KDE numerator has no adjoint");
@@ -635,7 +706,8 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
 #pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) accg[p] = 0;
   unsigned int flags = 0;
-  for (int e = tid; e < a.n_events; e += blockDim.x) {
+  const int slice = blockIdx.y, n_slices = gridDim.y;
+  for (int e = slice * blockDim.x + tid; e < a.n_events; e += n_slices * blockDim.x) {
     Part3 m{0, 0, 0};
     double G[GRAD ? 16 : 1];
 #pragma unroll
@@ -693,7 +765,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
 #pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) Gs[p] = 0;
 #pragma unroll 4
-  for (int sl = a.inj_slot0 + tid; sl < a.inj_slot1; sl += blockDim.x) {
+  for (int sl = a.inj_slot0 + slice * blockDim.x + tid; sl < a.inj_slot1; sl += n_slices * blockDim.x) {
     Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
     if constexpr (GRAD) {
       if (x.S1 > 0) {
@@ -759,51 +831,56 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     __syncthreads();
   }
   if (tid == 0) {
-    const Part3 s = rp[0];
-    unsigned int f = fl[0];
-    double logL = -INFINITY;
-    double lna = -INFINITY;
-    if (!valid) f |= 1u;
-    if (valid && s.S1 > 0) lna = log(s.S1) + s.R * ln2 - a.ln_ndraw;
-    else if (valid) f |= 4u;
-    if (f == 0) {
-      logL = red[0] - (double)a.n_events * lna;
-      if (!isfinite(logL)) {
-        f |= 8u;
-        logL = -INFINITY;
-      }
-    }
-    a.logL[b] = logL;
-    if (a.neff_sel) a.neff_sel[b] = s.S1 > 0 ? s.S1 * s.S1 / s.S2 : 0.0;
-    if (a.flags) a.flags[b] = f;
-    if constexpr (GRAD) {
-      if (a.grad) {
-        // basis totals T_j = sum_i B_ij / S1_i - N_det B_sel,j / S1_sel, then the map
-        double T[16];
-        for (int p = 0; p < 16; ++p) T[p] = (f == 0) ? redg[p][0] - (double)a.n_events * gsel[p][0] / s.S1 : 0.0;
-        const double* c = a.gmap + (size_t)b * N_GMAP;
-        const double T1 = nused[0] - (double)a.n_events;   // coefficient of the constant 1/H0 term
-        double g[16];
-        g[0] = c[0] * T1 + T[0];
-        g[1] = T[1];
-        g[2] = c[1] * T[2] - T[3];
-        g[3] = T[4];
-        g[4] = c[2] * T[2] + c[3] * T[5] + c[4] * T[6] - T[7];
-        g[5] = c[5] * T[2] + c[6] * T[5] + c[7] * T[6];
-        g[6] = T[8];
-        g[7] = c[8] * T[5] + c[12] * T[9];
-        g[8] = c[9] * T[5] + c[13] * T[10];
-        g[9] = c[10] * T[6] + c[14] * T[11];
-        g[10] = c[11] * T[6] + c[15] * T[12];
-        g[11] = -c[16] * T[2] + c[17] * (T[5] + T[6]);
-        g[12] = c[18] * T[5] - c[19] * T[6];
-        g[13] = c[21] * T[13] - T[14];
-        g[14] = -T[14];
-        g[15] = c[20] * T[15];
-        for (int p = 0; p < 16; ++p) a.grad[(size_t)b * 16 + p] = (f == 0) ? g[p] : 0.0;
+    if (n_slices == 1) {
+      combine_finish<GRAD>(a, b, red[0], nused[0], fl[0], GRAD ? &redg[0][0] : nullptr, 256, rp[0],
+                           GRAD ? &gsel[0][0] : nullptr, 256);
+    } else {
+      // slice record: acc, n_used, flags, selection (R, S1, S2), then 16 + 16 basis sums
+      double* o = a.cpart + ((size_t)b * n_slices + slice) * NF_CSLICE;
+      o[0] = red[0];
+      o[1] = nused[0];
+      o[2] = (double)fl[0];
+      o[3] = rp[0].R;
+      o[4] = rp[0].S1;
+      o[5] = rp[0].S2;
+      if constexpr (GRAD) {
+        for (int p = 0; p < 16; ++p) {
+          o[6 + p] = redg[p][0];
+          o[22 + p] = gsel[p][0];
+        }
       }
     }
   }
+}
+
+// Merge of the slices of one point in slice order (one thread per point).
+template <bool GRAD>
+__global__ __launch_bounds__(64) void combine_slices_kernel(CombineArgs a, int n_slices) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  double acc = 0, nused = 0;
+  unsigned int fl = 0;
+  Part3 sel{0, 0, 0};
+  double G[GRAD ? 16 : 1], Gs[GRAD ? 16 : 1];
+  for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = Gs[p] = 0;
+  for (int sl = 0; sl < n_slices; ++sl) {
+    const double* o = a.cpart + ((size_t)b * n_slices + sl) * NF_CSLICE;
+    acc += o[0];
+    nused += o[1];
+    fl |= (unsigned int)o[2];
+    const Part3 x{o[3], o[4], o[5]};
+    if constexpr (GRAD) {
+      for (int p = 0; p < 16; ++p) G[p] += o[6 + p];
+      const bool hs = sel.S1 > 0, hx = x.S1 > 0;
+      if (hx) {
+        const double Rm = hs ? fmax(sel.R, x.R) : x.R;
+        for (int p = 0; p < 16; ++p)
+          Gs[p] = (hs ? ldexp(Gs[p], (int)(sel.R - Rm)) : 0.0) + ldexp(o[22 + p], (int)(x.R - Rm));
+      }
+    }
+    sel = pmerge(sel, x);
+  }
+  combine_finish<GRAD>(a, b, acc, nused, fl, G, 1, sel, Gs, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,10 +928,10 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
                         void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st) {
   if (fp32)
-    setup_kernel<float><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
+    setup_kernel<float><<<dim3(B, 2), 256, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
                                             (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
   else
-    setup_kernel<double><<<B, 256, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
+    setup_kernel<double><<<dim3(B, 2), 256, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
                                              (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
   return hipGetLastError();
 }
@@ -920,9 +997,16 @@ hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
-  if (a.kde) combine_kernel<false, true><<<a.B, 256, 0, st>>>(a);
-  else if (grad) combine_kernel<true><<<a.B, 256, 0, st>>>(a);
-  else combine_kernel<false><<<a.B, 256, 0, st>>>(a);
+  const dim3 grid(a.B, a.n_slices);
+  if (a.kde) combine_kernel<false, true><<<grid, 256, 0, st>>>(a);
+  else if (grad) combine_kernel<true><<<grid, 256, 0, st>>>(a);
+  else combine_kernel<false><<<grid, 256, 0, st>>>(a);
+  if (a.n_slices > 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (grad && !a.kde) combine_slices_kernel<true><<<(a.B + 63) / 64, 64, 0, st>>>(a, a.n_slices);
+    else combine_slices_kernel<false><<<(a.B + 63) / 64, 64, 0, st>>>(a, a.n_slices);
+  }
   return hipGetLastError();
 }
 

@@ -151,6 +151,63 @@ def test_config4_kde_sampled(mods):
     lik.close()
 
 
+def test_config4_spectral_sampled(mods):
+    """O5-like catalogue at full size with the comoving-volume redshift prior
+    (spectral sirens) in the benchmark's launch (64 points, ln L + gradient):
+    sampled events against the oracle, and ln alpha of one point over all 1e7
+    injections."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    log("[c4 full spectral: generate]")
+    cat = synth.make_catalog("c4")
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision="fp32", z_prior="comoving")
+    lam = synth.lambdas_for("c4")
+    r = lik.loglike_grad(torch.tensor(lam, device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    lg = r["logL"].cpu().numpy()
+    ev = r["logL_event"].cpu().numpy()
+    ne = r["neff_event"].cpu().numpy()
+    rng = np.random.default_rng(12)
+    events = np.sort(rng.choice(cat.n_events, 5, replace=False))
+    sub = cat.subset(events, inj=slice(0, 1000))
+    n_amb = 0
+    for b in [0, 31, 63]:
+        ref = O.loglike(sub, lam[b], margins=True, z_prior="comoving")
+        refc = dict(logL_event=ref["logL_event"], neff_event=ref["neff_event"],
+                    gate_margin=ref["gate_margin"], sample_margin=ref["sample_margin"])
+        n_amb += check_events(ev[b, events], ne[b, events], refc, TOL_LOGL_FP32)
+    log(f"  sampled events {events.tolist()} ok, ambiguous {n_amb}")
+    b = 0
+    if math.isfinite(lg[b]):
+        ref = O.loglike(cat.subset([0]), lam[b], z_prior="comoving")
+        ln_a = _gpu_ln_alpha(lg[b], ev[b], cat.n_events)
+        log(f"  ln alpha gpu {ln_a!r} oracle {ref['ln_alpha']!r}")
+        assert abs(ln_a - ref["ln_alpha"]) < 1e-6 * max(1.0, abs(ref["ln_alpha"]))
+    lik.close()
+
+
+def test_config2_downsampled(mods):
+    """The 140-event catalogue with at most 40 samples per pixel kept at upload:
+    the whole likelihood against the oracle on the catalogue downsampled by the
+    same rule."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    log("[c2 downsampled 40/pixel]")
+    cat = synth.make_catalog("c2")
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision="fp32", max_samples_per_pixel=40,
+                                              downsample_seed=2605)
+    ds = O.downsample(cat, 40, seed=2605)
+    assert int(lik.info("n_samp")) == ds.n_samp
+    log(f"  kept {ds.n_samp} of {cat.n_samp} samples")
+    lam = synth.fiducial_lambda()
+    r = lik.loglike(torch.tensor(lam[None], device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    ref = O.loglike(ds, lam, margins=True)
+    assert int(r["flags"][0]) == ref["flags"] == 0
+    assert rel_close(float(r["logL"][0]), ref["logL"], TOL_LOGL_FP32)
+    n_amb = check_events(r["logL_event"][0].cpu().numpy(), r["neff_event"][0].cpu().numpy(), ref, TOL_LOGL_FP32)
+    assert n_amb <= max(3, cat.n_events // 20)
+    lik.close()
+
+
 def test_config5_gradient(mods):
     """Adjoint on the config-1 catalogue (64 points per launch) and on a 50-event
     subset of config 2, against the oracle's autograd gradient."""
