@@ -700,7 +700,7 @@ int dsl_set_option(dsl_handle* h, const char* key, double v) {
     if (v != 0 && v != 1 && v != 2) return fail(DSL_EINVAL, "kde_bandwidth must be 0 (Scott), 1 (Silverman) or 2 (biweight)");
     h->kde_bandwidth = (int)v;
   } else if (k == "kde_grid") {
-    if (v != (int)v || v < 2 || v > 64 * KDE_NPL_MAX) return fail(DSL_EINVAL, "kde_grid must be an integer in [2, 1024]");
+    if (v != (int)v || v < 2 || v > KDE_GRID_MAX) return fail(DSL_EINVAL, "kde_grid must be an integer in [2, 1024]");
     h->kde_grid = (int)v;
   } else if (k == "timing") {
     h->timing = v != 0;

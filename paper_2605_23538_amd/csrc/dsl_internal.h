@@ -120,8 +120,8 @@ struct SweepArgs {
 // 2^-R; T = integral of KDE x redshift prior x rate over the pixel's grid (0
 // when the pixel fails the gate), S1/S2 the Eq. (8) sums of its weights.
 constexpr int NF_KDE = 4;
-// Grid nodes per lane of the KDE kernel (the grid has at most 64 * KDE_NPL_MAX nodes).
-constexpr int KDE_NPL_MAX = 16;
+// Largest redshift grid of the KDE numerator.
+constexpr int KDE_GRID_MAX = 1024;
 
 struct KdeArgs {
   const void* samp;          // Samp<T>[n_samp]
@@ -137,7 +137,7 @@ struct KdeArgs {
   const void* win_tab;       // [B][NW+1] of T2
   int32_t B;
   int32_t bandwidth;         // 0 Scott, 1 Silverman, 2 biweight
-  int32_t n_grid;            // grid nodes (2 ... 64 * KDE_NPL_MAX)
+  int32_t n_grid;            // grid nodes (2 ... KDE_GRID_MAX)
   double tau;                // grid margin in bandwidths
   double neff_min;
   int32_t gate_mode;

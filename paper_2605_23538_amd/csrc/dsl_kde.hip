@@ -63,6 +63,17 @@ __device__ __forceinline__ double wave_sum(double x) {
   return wave_reduce(x, [](double a, double b) { return a + b; });
 }
 
+// Reduction over each 16-lane row (pairs, quads, half rows, rows): every lane
+// of a row ends with its row's result; rows do not mix.
+template <typename V, typename Op>
+__device__ __forceinline__ V row_reduce(V x, Op op) {
+  x = op(x, dpp<0xB1, 0xf>(x));    // quad_perm [1,0,3,2]
+  x = op(x, dpp<0x4E, 0xf>(x));    // quad_perm [2,3,0,1]
+  x = op(x, dpp<0x141, 0xf>(x));   // row_half_mirror
+  x = op(x, dpp<0x140, 0xf>(x));   // row_mirror
+  return x;
+}
+
 // Linear interpolation of a redshift-prior row at z in [0, z_max].
 template <typename T>
 __device__ __forceinline__ T los_at(const float* __restrict__ row, int n_z, T inv_dz, T z) {
@@ -83,17 +94,26 @@ __device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
   return M::exp2((c.gm3 + (T)2) * L - fmax(eX, (T)0)) * M::rcp((T)1 + M::exp2(-fabs(eX)));
 }
 
-// One wavefront per (pixel, point).  Pass A (lanes = samples): Eq. (7)
+// One wavefront per (pixel, group of four points): lane 16q + k serves point q
+// of the group, and each 16-lane DPP row reduces its own point's sums (no
+// cross-row traffic).  Pass A (a row's lanes stride over the samples): Eq. (7)
 // weights without prior and rate, Eq. (8) sums, in-support redshift moments
 // and range.  Bandwidth from the in-support redshifts (order statistics in
-// ascending d_L order, which is ascending z for any point).  Pass B (lanes =
-// grid nodes, NPL per lane): f(z_g) = sum_k w_k exp(-(z_g - z_k)^2 / 2h^2),
-// then T = dz / (h sqrt(2 pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with
-// trapezoid weights c_g.  Points of one tile (LT) share the block's tables.
-template <typename T, int LT, int NPL>
-__global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
+// ascending d_L order, which is ascending z for any point).  Pass B (each lane
+// holds 16 grid nodes of its point per block of 256 nodes): f(z_g) = sum_k w_k
+// exp(-(z_g - z_k)^2 / 2h^2) over the row's samples, then T = dz / (h sqrt(2
+// pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with trapezoid weights c_g.
+// Points of one tile (LT) share the block's tables.
+// FP32: 4 waves per SIMD (a few registers spill; measured faster than 3 waves
+// without spills); FP64: 2.
+template <typename T> struct KdeWaves { static constexpr int W = 4; };
+template <> struct KdeWaves<double> { static constexpr int W = 2; };
+
+template <typename T, int LT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>::W))) void kde_kernel(KdeArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
+  constexpr int NB = 16;   // grid nodes per lane per block of 256 nodes
   extern __shared__ __align__(16) unsigned char smem[];
   T2* cosL = reinterpret_cast<T2*>(smem);
   T2* winL = cosL + (NU + 1) * LT;
@@ -111,40 +131,39 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, kl = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nwaves = blockDim.x >> 6;
   const LamC<T>* lamc = reinterpret_cast<const LamC<T>*>(a.lamc);
   const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
   const TabView<T> tv{cosL, winL, nullptr};
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
-  const int64_t n_tasks = a.n_pix * nl;
-  unsigned long long evals = 0;   // uniform per wavefront
+  const int ng = (nl + 3) >> 2;   // groups of four points in this tile
+  const int64_t n_tasks = a.n_pix * ng;
+  unsigned long long evals = 0;   // kept by the first lane of each row
   for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
-    const int64_t p = t / nl;
-    const int l = (int)(t - p * nl);
-    const int b = tile * LT + l;
+    const int64_t p = t / ng;
+    const int l = 4 * (int)(t - p * ng) + q;   // this row's point in the tile
+    const bool act = l < nl;
+    const int b = tile * LT + (act ? l : 0);
     const LamC<T> c = lamc[b];
+    const bool live = act && c.valid;
     double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
     const int64_t s0 = a.pix_off[p];
     const int n = (int)(a.pix_off[p + 1] - s0);
-    if (!c.valid || n == 0) {
-      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
-      continue;
-    }
     // ---- pass A
     PixAcc<false, T> pa;
     pa.zero();
     double sz = 0.0, szz = 0.0;   // in-support redshift moments
     T zlo = (T)INFINITY, zhi = (T)-INFINITY;
-    int nin = 0;
-    T z1 = (T)-1, lin1 = (T)0;   // the lane's sample when n <= 64
+    int cin = 0;
+    T z1 = (T)-1, lin1 = (T)0;    // the lane's sample when n <= 16
     int ne1 = R_SENTINEL;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      const int k = c0 + lane;
-      T z = (T)-1;
-      if (k < n) {
+    for (int c0 = 0; c0 < n; c0 += 16) {
+      const int k = c0 + kl;
+      if (k < n && live) {
         int ne;
-        T lin;
+        T lin, z;
         eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
         pa.template add<T>(ne, lin, nullptr);
         if (z >= (T)0) {
@@ -152,42 +171,39 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
           szz += (double)z * (double)z;
           zlo = fmin(zlo, z);
           zhi = fmax(zhi, z);
+          ++cin;
         }
         z1 = z;
         lin1 = lin;
         ne1 = ne;
       }
-      nin += (int)__popcll(__ballot(z >= (T)0));
     }
-    const int R = wave_reduce(pa.R, [](int x, int y) { return x > y ? x : y; });
-    const double S1 = wave_sum(ldexp(pa.S1, pa.R - R));
-    const double S2 = wave_sum(ldexp(pa.S2, 2 * (pa.R - R)));
+    const int R = row_reduce(pa.R, [](int x, int y) { return x > y ? x : y; });
+    const double S1 = row_reduce(ldexp(pa.S1, pa.R - R), [](double x, double y) { return x + y; });
+    const double S2 = row_reduce(ldexp(pa.S2, 2 * (pa.R - R)), [](double x, double y) { return x + y; });
     bool pass;
-    if (a.gate_mode == 2) pass = S1 > 0;
-    else pass = S2 > 0 && S1 * S1 >= a.neff_min * S2;
-    if (!pass) {
-      if (lane == 0) out[0] = out[1] = out[2] = out[3] = 0.0;
-      continue;
-    }
-    sz = wave_sum(sz);
-    szz = wave_sum(szz);
-    zlo = wave_reduce(zlo, [](T x, T y) { return fmin(x, y); });
-    zhi = wave_reduce(zhi, [](T x, T y) { return fmax(x, y); });
-    // ---- bandwidth (Appendix D) from the n_in in-support redshifts
-    auto zs = [&](int r) -> double {   // r-th smallest in-support redshift (uniform)
+    if (a.gate_mode == 2) pass = live && S1 > 0;
+    else pass = live && S2 > 0 && S1 * S1 >= a.neff_min * S2;
+    sz = row_reduce(sz, [](double x, double y) { return x + y; });
+    szz = row_reduce(szz, [](double x, double y) { return x + y; });
+    zlo = row_reduce(zlo, [](T x, T y) { return fmin(x, y); });
+    zhi = row_reduce(zhi, [](T x, T y) { return fmax(x, y); });
+    const int nin = row_reduce(cin, [](int x, int y) { return x + y; });
+    // ---- bandwidth (Appendix D) from the n_in in-support redshifts of the row's point
+    auto zs = [&](int r) -> double {   // r-th smallest in-support redshift
       const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
       return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
     };
     auto z_w = [&](int c0, T& z, T& w) {   // the lane's redshift and scaled weight in chunk c0
-      if (n <= 64) {
+      if (n <= 16) {
         z = z1;
         w = (z1 >= (T)0 && lin1 > (T)0) ? ldexp(lin1, ne1 - R) : (T)0;
         return;
       }
-      const int k = c0 + lane;
+      const int k = c0 + kl;
       z = (T)-1;
       w = (T)0;
-      if (k < n) {
+      if (k < n && live) {
         int ne;
         T lin;
         eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
@@ -195,20 +211,20 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
       }
     };
     double h = 0.0;
-    if (nin >= 2 && zlo < zhi) {   // equal redshifts: zero spread, zero bandwidth
+    if (pass && nin >= 2 && zlo < zhi) {   // equal redshifts: zero spread, zero bandwidth
       const double sd = sqrt(fmax(szz - sz * sz / (double)nin, 0.0) / (double)(nin - 1));
       const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));   // n^(-1/5)
       if (a.bandwidth == 0) {
         h = 1.06 * sd * nf;
       } else if (a.bandwidth == 1) {
-        auto q = [&](double pr) {
+        auto qt = [&](double pr) {
           const double pos = pr * (double)(nin - 1);
           const int i0 = (int)floor(pos);
           const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
           const double z0 = zs(i0);
           return z0 + (pos - (double)i0) * (zs(i1) - z0);
         };
-        h = 0.9 * fmin(sd, (q(0.75) - q(0.25)) / 1.34) * nf;
+        h = 0.9 * fmin(sd, (qt(0.75) - qt(0.25)) / 1.34) * nf;
       } else {
         const int m = (nin - 1) / 2;
         const double Q = 0.5 * (zs(m) + zs(nin / 2));
@@ -233,7 +249,7 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
         if (mad > 0.0) {
           const double iu = 1.0 / (9.0 * mad);
           double num = 0.0, den = 0.0;
-          for (int c0 = 0; c0 < n; c0 += 64) {
+          for (int c0 = 0; c0 < n; c0 += 16) {
             T z, w;
             z_w(c0, z, w);
             if (z >= (T)0) {
@@ -245,79 +261,83 @@ __global__ __launch_bounds__(512) void kde_kernel(KdeArgs a) {
               }
             }
           }
-          num = wave_sum(num);
-          den = wave_sum(den);
+          num = row_reduce(num, [](double x, double y) { return x + y; });
+          den = row_reduce(den, [](double x, double y) { return x + y; });
           const double bm = (double)nin * num / (den * den);
           h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
         }
       }
     }
     const float* __restrict__ row = a.los + (size_t)a.pix_row[p] * a.n_z;
+    const bool kde_row = pass && h > 0.0 && isfinite(h);
     double Tt = 0.0;
-    if (!(h > 0.0) || !isfinite(h)) {
+    if (pass && !kde_row) {
       // zero bandwidth: point masses at the samples
-      for (int c0 = 0; c0 < n; c0 += 64) {
+      for (int c0 = 0; c0 < n; c0 += 16) {
         T z, w;
         z_w(c0, z, w);
         if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(c, z));
       }
-      Tt = wave_sum(Tt);
-    } else {
-      // ---- pass B: grid nodes g = lane + 64 i
+      Tt = row_reduce(Tt, [](double x, double y) { return x + y; });
+    } else if (kde_row) {
+      // ---- pass B
       const double ga = fmax(0.0, (double)zlo - a.tau * h);
       const double gb = fmin(a.z_max, (double)zhi + a.tau * h);
       const double dz = (gb - ga) / (double)(a.n_grid - 1);
       // coordinates scaled by sqrt(log2(e)/2)/h, so each term is exp2(-(x_g - x_k)^2)
       const T invh = (T)(sqrt(0.5 * LOG2E) / h);
-      T zgs[NPL], vg[NPL];
-      double accd[NPL];
+      for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
+        T zgs[NB], vg[NB];
 #pragma unroll
-      for (int i = 0; i < NPL; ++i) {
-        const int g = lane + 64 * i;
-        accd[i] = 0.0;
-        zgs[i] = (T)0;
-        vg[i] = (T)0;
-        if (g < a.n_grid) {
-          const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
-          const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
-          zgs[i] = zg * invh;
-          vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
-        }
-      }
-      for (int c0 = 0; c0 < n; c0 += 64) {
-        T z, w;
-        z_w(c0, z, w);
-        const T zsc = z * invh;
-        const int cnt = n - c0 < 64 ? n - c0 : 64;
-        T accf[NPL];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) accf[i] = (T)0;
-        evals += (unsigned long long)__popcll(__ballot(w > (T)0)) * (unsigned long long)a.n_grid;
-        // zero weights (out of support) add exact zeros: no per-sample branch
-        for (int j = 0; j < cnt; ++j) {
-          const T wj = rdlane(w, j);
-          const T zj = rdlane(zsc, j);
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            const T x = zgs[i] - zj;
-            accf[i] = fma(wj, Mth<T>::exp2(-(x * x)), accf[i]);
+        for (int i = 0; i < NB; ++i) {
+          const int g = g0 + kl + 16 * i;
+          zgs[i] = (T)0;
+          vg[i] = (T)0;
+          if (g < a.n_grid) {
+            const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
+            const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
+            zgs[i] = zg * invh;
+            vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
           }
         }
+        for (int c0 = 0; c0 < n; c0 += 16) {
+          T z, w;
+          z_w(c0, z, w);
+          const T zsc = z * invh;
+          const int cnt = n - c0 < 16 ? n - c0 : 16;
+          if (g0 == 0) {
+            const unsigned long long m = __ballot(w > (T)0);
+            if (kl == 0) evals += (unsigned long long)__popcll((m >> (16 * q)) & 0xffffull) * a.n_grid;
+          }
+          T accf[NB];
 #pragma unroll
-        for (int i = 0; i < NPL; ++i) accd[i] += (double)accf[i];
+          for (int i = 0; i < NB; ++i) accf[i] = (T)0;
+          // zero weights (out of support) add exact zeros: no per-sample branch
+          for (int j = 0; j < cnt; ++j) {
+            const T wj = __shfl(w, j, 16);
+            const T zj = __shfl(zsc, j, 16);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+              const T x = zgs[i] - zj;
+              accf[i] = fma(wj, Mth<T>::exp2(-(x * x)), accf[i]);
+            }
+          }
+          double part = 0.0;
+#pragma unroll
+          for (int i = 0; i < NB; ++i) part += (double)vg[i] * (double)accf[i];
+          Tt += part;
+        }
       }
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) Tt += (double)vg[i] * accd[i];
-      Tt = wave_sum(Tt) * dz / (h * 2.5066282746310002);
+      Tt = row_reduce(Tt, [](double x, double y) { return x + y; }) * dz / (h * 2.5066282746310002);
     }
-    if (lane == 0) {
-      out[0] = (double)R;
-      out[1] = Tt;
-      out[2] = S1;
-      out[3] = S2;
+    if (act && kl == 0) {
+      out[0] = pass ? (double)R : 0.0;
+      out[1] = pass ? Tt : 0.0;
+      out[2] = pass ? S1 : 0.0;
+      out[3] = pass ? S2 : 0.0;
     }
   }
-  if (a.evals && lane == 0 && evals) atomicAdd(a.evals, evals);
+  if (a.evals && kl == 0 && evals) atomicAdd(a.evals, evals);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
@@ -377,9 +397,9 @@ static size_t kde_lds_bytes() {
   return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
 }
 
-template <typename T, int NPL>
+template <typename T>
 static hipError_t kde_attr() {
-  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, NPL>,
+  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
 }
 
@@ -387,16 +407,12 @@ template <typename T>
 static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
   constexpr int LT = KdeTile<T>::LT;
   const int n_tiles = (a.B + LT - 1) / LT;
-  const int64_t tasks = a.n_pix * (a.B < LT ? a.B : LT);
+  const int64_t tasks = a.n_pix * ((a.B < LT ? a.B : LT) + 3) / 4;
   int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
   if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
   if (grid_x < 1) grid_x = 1;
-  const dim3 grid(grid_x, n_tiles);
-  const size_t lds = kde_lds_bytes<T>();
-  if (a.n_grid <= 256) kde_kernel<T, LT, 4><<<grid, 512, lds, st>>>(a);
-  else if (a.n_grid <= 512) kde_kernel<T, LT, 8><<<grid, 512, lds, st>>>(a);
-  else if (a.n_grid <= 64 * KDE_NPL_MAX) kde_kernel<T, LT, KDE_NPL_MAX><<<grid, 512, lds, st>>>(a);
-  else return hipErrorInvalidValue;
+  if (a.n_grid < 2 || a.n_grid > KDE_GRID_MAX) return hipErrorInvalidValue;
+  kde_kernel<T, LT><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
   return hipGetLastError();
 }
 
@@ -420,12 +436,8 @@ hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64
 // Raise the dynamic-LDS limit of every KDE variant (once, outside any capture).
 hipError_t init_kde_attrs() {
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = kde_attr<float, 4>();
-  if (e == hipSuccess) e = kde_attr<float, 8>();
-  if (e == hipSuccess) e = kde_attr<float, KDE_NPL_MAX>();
-  if (e == hipSuccess) e = kde_attr<double, 4>();
-  if (e == hipSuccess) e = kde_attr<double, 8>();
-  if (e == hipSuccess) e = kde_attr<double, KDE_NPL_MAX>();
+  if (e == hipSuccess) e = kde_attr<float>();
+  if (e == hipSuccess) e = kde_attr<double>();
   return e;
 }
 
