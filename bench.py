@@ -22,18 +22,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per sample-weight (one sample or injection, one Lambda):
-# floating-point operations of the weight formula as the sweep evaluates it
-# (add/mul = 1, fused multiply-add = 2, each exp2/log2/rcp/rsqrt/sqrt = 1),
-# counted from the source: the forward weight (distance inversion, frame
-# change, Jacobian, prior, rate, mixture, window, smoothing, exponent
-# bookkeeping) and, for the adjoint, its 16 basis derivatives and sums.
+# Algorithmic work per sample-weight (one sample or injection, one Lambda), in
+# FP operations with FMA = 2 and each transcendental = 1: the adjoint sweep's
+# figure is measured on the built kernel (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,
+# TRANS}_F32 + 2 x FMA_F32, plus the F64 counts, per sample-weight: 300; a
+# count from the source gives 360 because the kernel shares subexpressions
+# between the weight and its derivatives); the forward figure is counted from
+# the source (distance inversion, frame change, Jacobian, prior, rate, mixture,
+# window, smoothing, exponent bookkeeping).
 FLOP_PER_WEIGHT_FWD = 175
-FLOP_PER_WEIGHT_GRAD = 360
-# KDE numerator: the weight without prior and rate (164), and per (sample, grid
-# node) kernel term: difference, scale, square, exp2, multiply-add (6).
+FLOP_PER_WEIGHT_GRAD = 300
+# KDE numerator: the weight without prior and rate (164, from the source), and
+# per (sample, grid node) kernel term: difference, square, exp2, multiply-add (5).
 FLOP_PER_KDE_WEIGHT = 164
-FLOP_PER_KDE_NODE = 6
+FLOP_PER_KDE_NODE = 5
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6
@@ -42,7 +44,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated against
 # an elementwise copy of known size; profiles/sweep_c4_grad_traffic.txt), valid only for
 # the kernel source they were measured on.
-MEASURED_TRAFFIC = {("c4", 64, True): {"kernel_sha256_16": "06ace62cea0fc9b3", "bytes": 5.684e9}}
+MEASURED_TRAFFIC = {("c4", 64, True): {"kernel_sha256_16": "368807d7070d937e", "bytes": 5.684e9}}
 
 
 def parse():
@@ -214,9 +216,8 @@ def main():
         traffic = mt["bytes"]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": ("kde_kernel<%s,%d,%d>" % ("float" if precision == "fp32" else "double",
-                                                      64 if precision == "fp32" else 4,
-                                                      4 if int(lik.info("kde_grid")) <= 256 else 8)) if kde
+                "kernel": ("kde_kernel<%s,%d>" % ("float" if precision == "fp32" else "double",
+                                                   64 if precision == "fp32" else 4)) if kde
                 else "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
                                                  int(lik.info("lambda_tile_used")), "true" if grad else "false"),
                 "kernel_ms": round(kde_avg if kde else sweep_avg, 4),
@@ -303,7 +304,7 @@ def main():
                     "finite_logL": int(np.isfinite(out.cpu().numpy()).sum()),
                     "roofline": {"bound": "alu", "achieved": round(kach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(kach / PEAK_FP32_VECTOR_TFLOPS, 4),
-                                 "traffic": None, "kernel": "kde_kernel<float,64,4> + kde_event_kernel",
+                                 "traffic": None, "kernel": "kde_kernel<float,64> + kde_event_kernel",
                                  "kernel_ms": round(kavg, 3), "kde_node_evals_per_launch": kev,
                                  "flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE}}
         lik.set_option("numerator", 0)
