@@ -390,6 +390,13 @@ SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   if (!h->fp32 && c.GL > 4) c.GL = 4;
   if (h->chunk_opt) c.chunk = h->chunk_opt;
   if (c.chunk <= 0) c.chunk = auto_chunk(h, c.GL);
+  if (it == h->tuned.end() || h->lambda_tile) {
+    // the 64-point FP32 adjoint tables take 117 KB of LDS, one workgroup per CU:
+    // 12 wavefronts (3 per SIMD) instead of 8
+    const bool big = h->fp32 && grad && c.GL == 64;
+    c.waves = big ? 12 : 8;
+    c.wg_per_cu = big ? 1 : 2;
+  }
   return c;
 }
 
@@ -566,7 +573,7 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   k.grad = grad;
   k.st = st;
   const void* ptrs[8] = {d_lambda, o.logL, o.grad, o.logL_event, o.neff_event, o.neff_sel, o.flags,
-                         (const void*)(intptr_t)(cfg.GL * 1000003 + cfg.chunk)};
+                         (const void*)(intptr_t)((cfg.GL * 1000003 + cfg.chunk) * 64 + cfg.waves)};
   std::memcpy(k.ptrs, ptrs, sizeof(ptrs));
   auto it = h->graphs.find(k);
   if (it == h->graphs.end()) {
@@ -853,10 +860,15 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
       ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
       if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
     }
+    const bool big = h->fp32 && grad && gl == 64;
+    for (int shape = 0; shape < (big ? 2 : 1) && !rc; ++shape)
     for (int64_t ch : chunks) {
+      if (rc) break;
       SweepCfg c;
       c.GL = gl;
       c.chunk = ch;
+      c.waves = (big && shape == 0) ? 12 : 8;
+      c.wg_per_cu = (big && shape == 0) ? 1 : 2;
       h->tuned[{B, grad ? 1 : 0}] = c;
       CallOut o{dout.as<double>(), grad ? dg.as<double>() : nullptr, nullptr, nullptr, nullptr, nullptr};
       if ((rc = run(h, dl.as<double>(), B, grad, o, nullptr))) break;   // warm-up (and build)

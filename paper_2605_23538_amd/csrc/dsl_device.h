@@ -98,7 +98,8 @@ __device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv,
 }
 
 // Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
-// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log).  With KW (the
+// support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log; not set where
+// lin = 0).  With KW (the
 // KDE numerator's weights) the redshift prior and the rate are left out of w
 // and *z_out receives the sample's redshift, or -1 beyond z_max.  SPEC selects
 // the comoving-volume redshift prior (spectral sirens) instead of the table.
@@ -196,11 +197,7 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   lin_out = ok ? lin : (T)0;
 
   if constexpr (GRAD) {
-    if (!ok) {
-#pragma unroll
-      for (int p = 0; p < 16; ++p) g[p] = (T)0;
-      return;
-    }
+    // (lanes outside the support have lin = 0: their basis is never accumulated)
     const T Q = M::rcp(losv * mixf);          // 1/(los mix)
     const T rmix = Q * losv, rlos = Q * mixf;
     const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;

@@ -462,8 +462,15 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
 // ---------------------------------------------------------------------------
 // sweep
 // ---------------------------------------------------------------------------
+// Largest workgroup of a sweep variant: 768 threads (12 wavefronts, 3 per SIMD)
+// for the FP32 64-point adjoint, whose 117 KB of LDS tables allow one workgroup
+// per CU; 512 otherwise.
+template <typename T, int GL, bool GRAD>
+struct SweepMaxThreads { static constexpr int N = (sizeof(T) == 4 && GL == 64 && GRAD) ? 768 : 512; };
+
 template <typename T, int GL, bool GRAD, bool SPEC>
-__global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, GRAD>::N))) void sweep_kernel(
+    SweepArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
   constexpr int NF = GRAD ? NF_GRAD : NF_FWD;
@@ -494,7 +501,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepArgs a) {
   }
   __syncthreads();
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: item bounds stay scalar
   const int nwaves = blockDim.x >> 6;
   const int lam = lane % GL;
   const int sg = lane / GL;
