@@ -381,6 +381,19 @@ int default_gl(const dsl_handle* h, int B) {
   return 1;
 }
 
+// Workgroup shape of the sweep. The FP32 adjoint fits 3 waves per SIMD (<= 168
+// VGPRs): 64-point tiles take 117 KB of LDS, so one 12-wavefront workgroup per
+// CU; smaller tiles three 4-wavefront workgroups. Shape 1 is the plain 8 x 2.
+void block_shape(const dsl_handle* h, bool grad, int GL, int shape, SweepCfg& c) {
+  if (h->fp32 && grad && shape == 0) {
+    c.waves = GL == 64 ? 12 : 4;
+    c.wg_per_cu = GL == 64 ? 1 : 3;
+  } else {
+    c.waves = 8;
+    c.wg_per_cu = 2;
+  }
+}
+
 SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   auto it = h->tuned.find({B, grad ? 1 : 0});
   SweepCfg c;
@@ -390,13 +403,7 @@ SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   if (!h->fp32 && c.GL > 4) c.GL = 4;
   if (h->chunk_opt) c.chunk = h->chunk_opt;
   if (c.chunk <= 0) c.chunk = auto_chunk(h, c.GL);
-  if (it == h->tuned.end() || h->lambda_tile) {
-    // the 64-point FP32 adjoint tables take 117 KB of LDS, one workgroup per CU:
-    // 12 wavefronts (3 per SIMD) instead of 8
-    const bool big = h->fp32 && grad && c.GL == 64;
-    c.waves = big ? 12 : 8;
-    c.wg_per_cu = big ? 1 : 2;
-  }
+  if (it == h->tuned.end() || h->lambda_tile) block_shape(h, grad, c.GL, 0, c);
   return c;
 }
 
@@ -860,15 +867,14 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
       ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
       if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
     }
-    const bool big = h->fp32 && grad && gl == 64;
+    const bool big = h->fp32 && grad;
     for (int shape = 0; shape < (big ? 2 : 1) && !rc; ++shape)
     for (int64_t ch : chunks) {
       if (rc) break;
       SweepCfg c;
       c.GL = gl;
       c.chunk = ch;
-      c.waves = (big && shape == 0) ? 12 : 8;
-      c.wg_per_cu = (big && shape == 0) ? 1 : 2;
+      block_shape(h, grad, gl, shape, c);
       h->tuned[{B, grad ? 1 : 0}] = c;
       CallOut o{dout.as<double>(), grad ? dg.as<double>() : nullptr, nullptr, nullptr, nullptr, nullptr};
       if ((rc = run(h, dl.as<double>(), B, grad, o, nullptr))) break;   // warm-up (and build)

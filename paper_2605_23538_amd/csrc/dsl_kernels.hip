@@ -386,12 +386,13 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   }
 }
 
-// Item-level sums (FP64 throughout).
-template <bool GRAD>
+// Item-level sums: S1, S2 in FP64; the 16 adjoint basis sums in GT (FP32 for
+// the FP32 sweep, like the pixel-level ones: an item merges a few pixels).
+template <bool GRAD, typename GT = double>
 struct ItemAcc {
   int R;
   double S1, S2;
-  double G[GRAD ? 16 : 1];
+  GT G[GRAD ? 16 : 1];
   __device__ __forceinline__ void zero() {
     R = R_SENTINEL;
     S1 = 0;
@@ -407,7 +408,7 @@ struct ItemAcc {
     S2 = ldexp(S2, 2 * da) + ldexp(o.S2, 2 * db);
     if constexpr (GRAD) {
 #pragma unroll
-      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], da) + ldexp((double)o.G[p], db);
+      for (int p = 0; p < 16; ++p) G[p] = ldexp(G[p], da) + ldexp((GT)o.G[p], db);
     }
     R = Rm;
   }
@@ -462,11 +463,11 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
 // ---------------------------------------------------------------------------
 // sweep
 // ---------------------------------------------------------------------------
-// Largest workgroup of a sweep variant: 768 threads (12 wavefronts, 3 per SIMD)
-// for the FP32 64-point adjoint, whose 117 KB of LDS tables allow one workgroup
-// per CU; 512 otherwise.
+// Largest workgroup of a sweep variant: 768 threads (12 wavefronts, 3 per SIMD
+// at <= 168 VGPRs) for the FP32 adjoint -- the 64-point tables take 117 KB of
+// LDS, so one workgroup per CU -- and 512 otherwise.
 template <typename T, int GL, bool GRAD>
-struct SweepMaxThreads { static constexpr int N = (sizeof(T) == 4 && GL == 64 && GRAD) ? 768 : 512; };
+struct SweepMaxThreads { static constexpr int N = (sizeof(T) == 4 && GRAD) ? 768 : 512; };
 
 template <typename T, int GL, bool GRAD, bool SPEC>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, GRAD>::N))) void sweep_kernel(
@@ -519,7 +520,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
   for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
     const WorkItem w = a.items[a.order[it]];
     if (a.skip_events && w.event >= 0) continue;
-    ItemAcc<GRAD> chunk;
+    ItemAcc<GRAD, T> chunk;
     chunk.zero();
     int npass = 0;
     if (w.event >= 0 && w.pix1 == w.pix0) {
