@@ -133,6 +133,7 @@ struct dsl_handle {
   bool have_timing = false;
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  std::vector<const void*> ws_sig;   // workspace addresses the cached graphs were captured with
   std::map<std::pair<int, int>, SweepCfg> tuned;   // (B, grad) -> configuration
   ~dsl_handle() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -570,6 +571,15 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   int rc;
   if ((rc = build_items(h, cfg.chunk))) return rc;
   if ((rc = ensure_workspace(h, B, grad))) return rc;
+  // captured graphs hold workspace addresses: drop them all when any buffer moved
+  const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
+                                        h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
+                                        h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p};
+  if (sig != h->ws_sig) {
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->ws_sig = sig;
+  }
   if (h->timing) {
     h->have_timing = true;
     return enqueue(h, d_lambda, B, grad, o, cfg, st, true);

@@ -146,6 +146,40 @@ def test_determinism_and_graph_replay(mods):
     lik.close()
 
 
+def test_graphs_after_workspace_growth(mods):
+    """One handle, graph replay on, fixed output buffers per batch size, and
+    batches that grow and shrink (workspace reallocations in between): every
+    call equals an eager call of the same batch.  Captured graphs hold
+    workspace addresses, so they must be dropped when a buffer moves."""
+    import ctypes as C
+    torch, synth = mods["torch"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    eager = mods["binding"].DarkSirenLikelihood(cat)
+    eager.set_option("graph", 0)
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    lib = lik.lib
+    sizes = (16, 64, 130)
+    lam = {B: torch.tensor(synth.draw_lambdas(B, seed=B), device="cuda") for B in sizes}
+    out = {B: (torch.empty(B, dtype=torch.float64, device="cuda"), torch.empty(B, 16, dtype=torch.float64, device="cuda"))
+           for B in sizes}
+    ref = {}
+    for B in sizes:
+        r = eager.loglike_grad(lam[B])
+        ref[B] = (r["logL"].clone(), r["grad"].clone())
+    st = torch.cuda.current_stream().cuda_stream
+    for B in (16, 64, 16, 130, 64, 16, 130):
+        lo, go = out[B]
+        rc = lib.dsl_loglike_grad(lik.h, C.c_void_p(lam[B].data_ptr()), B, C.c_void_p(lo.data_ptr()),
+                                  C.c_void_p(go.data_ptr()), None, None, None, None, C.c_void_p(st))
+        assert rc == 0, lib.dsl_last_error().decode()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(lo, neginf=-1e300), torch.nan_to_num(ref[B][0], neginf=-1e300)), B
+        assert torch.equal(go, ref[B][1]), B
+    log("  7 graph-mode calls over batches 16/64/130 equal eager calls")
+    lik.close()
+    eager.close()
+
+
 def test_autograd_function(mods):
     torch, O, synth = mods["torch"], mods["O"], mods["synth"]
     cat = synth.make_catalog("c1", n_events=3, n_inj=3000)
