@@ -162,7 +162,8 @@ int dsl_create(const dsl_catalog_desc* desc, dsl_handle** out);
 int dsl_set_option(dsl_handle* h, const char* key, double value);
 
 /* Read back an option or a catalogue size ("n_events", "n_pix", "n_samp",
- * "n_inj", "n_items", "precision", ...), or, after a call made with option
+ * "n_inj", "n_items", "precision", ...), "lambda_tile_used" (the Lambda tile
+ * of the last call), "device_bytes" (device memory the handle holds), or, after a call made with option
  * "timing" = 1, "ms_sweep_only" (the weight sweep alone) and "ms_pixels" (the
  * per-pixel stage after it: the KDE kernel, or the gate of split pixels).
  * Returns DSL_EINVAL for unknown keys. */
@@ -200,7 +201,8 @@ int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_log
  * Choose the sweep configuration (Lambda tile, chunk) for batches of B points
  * by timing the candidates on the current device; the choice is cached in the
  * handle and, when cache_path is not NULL, appended to that text file (one
- * line per device/catalogue/B key; read first if it exists).
+ * line per device/catalogue/options/B key; read first if it exists, and a
+ * line whose configuration this library does not launch is ignored).
  */
 int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path);
 

@@ -278,8 +278,6 @@ int pack_samples(dsl_handle* h, DevBuf& out, const double* m1, const double* m2,
   return DSL_OK;
 }
 
-// Target samples per work item: about 16 items per CU for one-point tiles
-// (a wavefront then sweeps 64 samples per step), 64 per CU otherwise.
 // Default work-item size: about 256 items per compute unit for batched tiles
 // and 64 for one-point tiles (what the autotuner picks on the 33M- and
 // 3.6M-weight catalogues), at least 64 samples.
@@ -617,6 +615,91 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   return DSL_OK;
 }
 
+// Sweep configurations the autotuner may choose for batches of B points:
+// Lambda tiles (a tile is skipped when it would leave most lanes idle), chunks
+// about the automatic size, and for the FP32 adjoint both workgroup shapes.
+std::vector<SweepCfg> tune_candidates(const dsl_handle* h, int B, bool grad) {
+  std::vector<SweepCfg> out;
+  const std::vector<int> gls = h->fp32 ? std::vector<int>{1, 4, 16, 64} : std::vector<int>{1, 4};
+  for (int gl : gls) {
+    if (gl > 1 && B < gl / 4) continue;
+    const int64_t base = auto_chunk(h, gl);
+    std::vector<int64_t> chunks;
+    for (int64_t ch : {base / 16, base / 4, base, base * 4}) {
+      ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
+      if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
+    }
+    const int shapes = h->fp32 && grad ? 2 : 1;
+    for (int shape = 0; shape < shapes; ++shape)
+      for (int64_t ch : chunks) {
+        SweepCfg c;
+        c.GL = gl;
+        c.chunk = ch;
+        block_shape(h, grad, gl, shape, c);
+        out.push_back(c);
+      }
+  }
+  return out;
+}
+
+// A cached entry is taken only if its tile and workgroup shape are ones this
+// library launches and its chunk lies in the range the tuner explores.
+bool cached_cfg_ok(const dsl_handle* h, bool grad, const SweepCfg& c) {
+  if (c.chunk < 64 || c.chunk > 65536) return false;
+  if (!(c.GL == 1 || c.GL == 4 || (h->fp32 && (c.GL == 16 || c.GL == 64)))) return false;
+  for (int shape = 0; shape < 2; ++shape) {
+    SweepCfg s;
+    block_shape(h, grad, c.GL, shape, s);
+    if (s.waves == c.waves && s.wg_per_cu == c.wg_per_cu) return true;
+  }
+  return false;
+}
+
+// Times every candidate (one warm-up call, then three) and returns the fastest
+// in `best`.  The caller restores the handle's options.
+int tune_sweep(dsl_handle* h, int B, bool grad, SweepCfg& best) {
+  // scratch Lambda batch: the prior's centre replicated (valid everywhere)
+  std::vector<double> lam(16 * (size_t)B);
+  const double centre[16] = {70, 0.3, 2.9, 1.0, 4.6, 86.3, 4.8, 9.7, 0.7, 30.7, 6.3, 0.4, 0.8, 3.3, 2.9, 2.5};
+  for (int b = 0; b < B; ++b)
+    for (int p = 0; p < 16; ++p) lam[16 * b + p] = centre[p];
+  DevBuf dl, dout, dg;
+  if (dl.ensure(sizeof(double) * 16 * B) || dout.ensure(sizeof(double) * B) || dg.ensure(sizeof(double) * 16 * B))
+    return fail(DSL_ENOMEM, "autotune scratch");
+  HIPCHK(hipMemcpy(dl.p, lam.data(), sizeof(double) * 16 * B, hipMemcpyHostToDevice));
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIPCHK(hipEventCreate(&ev.e0));
+  HIPCHK(hipEventCreate(&ev.e1));
+  const std::pair<int, int> slot{B, grad ? 1 : 0};
+  CallOut o{dout.as<double>(), grad ? dg.as<double>() : nullptr, nullptr, nullptr, nullptr, nullptr};
+  double best_ms = 1e300;
+  for (const SweepCfg& c : tune_candidates(h, B, grad)) {
+    h->tuned[slot] = c;
+    int rc = run(h, dl.as<double>(), B, grad, o, nullptr);   // warm-up (and workspace)
+    if (rc) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipEventRecord(ev.e0, nullptr));
+    const int reps = 3;
+    for (int r = 0; r < reps; ++r)
+      if ((rc = run(h, dl.as<double>(), B, grad, o, nullptr))) return rc;
+    HIPCHK(hipEventRecord(ev.e1, nullptr));
+    HIPCHK(hipEventSynchronize(ev.e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = c;
+    }
+  }
+  return best_ms < 1e300 ? DSL_OK : fail(DSL_ESTATE, "autotune found no candidate");
+}
+
 }  // namespace
 
 extern "C" {
@@ -761,6 +844,8 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "kde_grid") *v = h->kde_grid;
   else if (k == "max_batch") *v = h->max_batch;
   else if (k == "lambda_tile") *v = h->lambda_tile;
+  else if (k == "graph") *v = h->graph;
+  else if (k == "timing") *v = h->timing;
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
   else if (k == "n_cu") *v = h->n_cu;
   else if (k == "lambda_tile_used") *v = h->last_gl;
@@ -826,10 +911,14 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
     HIPCHK(hipGetDeviceProperties(&prop, h->device));
     std::snprintf(devname, sizeof(devname), "%s", prop.gcnArchName);
   }
+  // everything the sweep's cost depends on, without spaces
   std::ostringstream keyss;
   keyss << devname << "|fp32=" << h->fp32 << "|grad=" << grad << "|B=" << B << "|samp=" << h->n_samp
-        << "|inj=" << h->n_inj << "|pix=" << h->n_pix << "|ev=" << h->n_events;
-  const std::string key = keyss.str();
+        << "|inj=" << h->n_inj << "|pix=" << h->n_pix << "|ev=" << h->n_events << "|zprior=" << h->z_prior
+        << "|num=" << h->numerator;
+  std::string key = keyss.str();
+  std::replace(key.begin(), key.end(), ' ', '_');
+  const std::pair<int, int> slot{B, grad ? 1 : 0};
   // cache lookup: one line per entry, "key GL chunk waves wg_per_cu"
   if (cache_path) {
     std::ifstream f(cache_path);
@@ -838,86 +927,33 @@ int dsl_autotune(dsl_handle* h, int B, int with_grad, const char* cache_path) {
       std::istringstream ls(line);
       std::string k;
       SweepCfg c;
-      if (ls >> k >> c.GL >> c.chunk >> c.waves >> c.wg_per_cu && k == key) {
-        h->tuned[{B, grad ? 1 : 0}] = c;
+      if (ls >> k >> c.GL >> c.chunk >> c.waves >> c.wg_per_cu && k == key && cached_cfg_ok(h, grad, c)) {
+        h->tuned[slot] = c;
         return DSL_OK;
       }
     }
   }
-  // candidates
-  std::vector<int> gls = h->fp32 ? std::vector<int>{1, 4, 16, 64} : std::vector<int>{1, 4};
-
-  // scratch Lambda batch: the prior's centre replicated (valid everywhere)
-  std::vector<double> lam(16 * (size_t)B);
-  const double centre[16] = {70, 0.3, 2.9, 1.0, 4.6, 86.3, 4.8, 9.7, 0.7, 30.7, 6.3, 0.4, 0.8, 3.3, 2.9, 2.5};
-  for (int b = 0; b < B; ++b)
-    for (int p = 0; p < 16; ++p) lam[16 * b + p] = centre[p];
-  DevBuf dl, dout, dg;
-  if (dl.ensure(sizeof(double) * 16 * B) || dout.ensure(sizeof(double) * B) || dg.ensure(sizeof(double) * 16 * B))
-    return fail(DSL_ENOMEM, "autotune scratch");
-  HIPCHK(hipMemcpy(dl.p, lam.data(), sizeof(double) * 16 * B, hipMemcpyHostToDevice));
-  const int saved_tile = h->lambda_tile;
+  const int saved_tile = h->lambda_tile, saved_graph = h->graph, saved_timing = h->timing;
   const int64_t saved_chunk = h->chunk_opt;
-  const int saved_graph = h->graph, saved_timing = h->timing;
   h->lambda_tile = 0;
   h->chunk_opt = 0;
   h->graph = 0;
   h->timing = 0;
   SweepCfg best;
-  double best_ms = 1e300;
-  int rc = DSL_OK;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  for (int gl : gls) {
-    if (gl > 1 && B < gl / 4) continue;   // mostly idle lanes
-    const int64_t base = auto_chunk(h, gl);
-    std::vector<int64_t> chunks;
-    for (int64_t ch : {base / 16, base / 4, base, base * 4}) {
-      ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
-      if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
-    }
-    const bool big = h->fp32 && grad;
-    for (int shape = 0; shape < (big ? 2 : 1) && !rc; ++shape)
-    for (int64_t ch : chunks) {
-      if (rc) break;
-      SweepCfg c;
-      c.GL = gl;
-      c.chunk = ch;
-      block_shape(h, grad, gl, shape, c);
-      h->tuned[{B, grad ? 1 : 0}] = c;
-      CallOut o{dout.as<double>(), grad ? dg.as<double>() : nullptr, nullptr, nullptr, nullptr, nullptr};
-      if ((rc = run(h, dl.as<double>(), B, grad, o, nullptr))) break;   // warm-up (and build)
-      HIPCHK(hipDeviceSynchronize());
-      HIPCHK(hipEventRecord(e0, nullptr));
-      const int reps = 3;
-      for (int r = 0; r < reps && !rc; ++r) rc = run(h, dl.as<double>(), B, grad, o, nullptr);
-      HIPCHK(hipEventRecord(e1, nullptr));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (rc) break;
-      if (ms / reps < best_ms) {
-        best_ms = ms / reps;
-        best = c;
-      }
-    }
-    if (rc) break;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  const int rc = tune_sweep(h, B, grad, best);
   h->lambda_tile = saved_tile;
   h->chunk_opt = saved_chunk;
   h->graph = saved_graph;
   h->timing = saved_timing;
   if (rc) {
-    h->tuned.erase({B, grad ? 1 : 0});
+    h->tuned.erase(slot);
     return rc;
   }
-  h->tuned[{B, grad ? 1 : 0}] = best;
+  h->tuned[slot] = best;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key << " " << best.GL << " " << best.chunk << " " << best.waves << " " << best.wg_per_cu << "\n";
+    if (!f) return fail(DSL_EINVAL, "cannot append to the autotune cache file");
   }
   return DSL_OK;
 }

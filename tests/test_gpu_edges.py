@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from tests.gpu_common import TOL_LOGL_FP32, check_events, log, need_gpu, rel_close
+from tests.gpu_common import TOL_LOGL_FP32, check_events, check_grad, log, need_gpu, rel_close
 
 pytestmark = pytest.mark.gpu
 
@@ -192,3 +192,49 @@ def test_autograd_function(mods):
     np.testing.assert_allclose(g[0], ref["grad"], rtol=1e-4, atol=1e-6 * np.linalg.norm(ref["grad"]))
     np.testing.assert_allclose(g[1], 2 * ref["grad"], rtol=1e-4, atol=2e-6 * np.linalg.norm(ref["grad"]))
     lik.close()
+
+
+def test_autotune_and_cache(mods, tmp_path):
+    """The autotuner's choice gives results at parity with the oracle, is
+    written to and read back from its cache file (a second handle takes it
+    without tuning and reproduces the first bitwise), leaves the caller's
+    options as they were, and ignores a cache line it does not launch."""
+    torch, O, synth, binding = mods["torch"], mods["O"], mods["synth"], mods["binding"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    lam_np = synth.draw_lambdas(16, seed=31)
+    lam_np[0] = synth.fiducial_lambda()
+    lam = torch.tensor(lam_np, device="cuda")
+    cache = tmp_path / "tune.txt"
+    a = binding.DarkSirenLikelihood(cat)
+    a.set_option("graph", 0)
+    a.autotune(16, grad=True, cache_path=str(cache))
+    assert a.info("graph") == 0 and a.info("lambda_tile") == 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    key, gl, chunk, waves, wg = lines[0].split()
+    ra = a.loglike_grad(lam)
+    torch.cuda.synchronize()
+    assert a.info("lambda_tile_used") == int(gl) and a.info("chunk") == int(chunk)
+    log(f"  tuned: tile {gl}, chunk {chunk}, {waves} waves x {wg} per CU")
+    for b in (0, 5):
+        ref = O.loglike(cat, lam_np[b], grad=True)
+        assert rel_close(float(ra["logL"][b]), ref["logL"], TOL_LOGL_FP32)
+        check_grad(ra["grad"][b].cpu().numpy(), ref["grad"])
+    # a second handle reads the entry (no new line) and reproduces the first
+    b2 = binding.DarkSirenLikelihood(cat)
+    b2.autotune(16, grad=True, cache_path=str(cache))
+    assert len(cache.read_text().splitlines()) == 1
+    rb = b2.loglike_grad(lam)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(rb["logL"], neginf=-1e300), torch.nan_to_num(ra["logL"], neginf=-1e300))
+    assert torch.equal(rb["grad"], ra["grad"])
+    b2.close()
+    # a line with a tile this library does not launch is ignored: the tuner runs again
+    cache.write_text(f"{key} 3 {chunk} {waves} {wg}\n")
+    c = binding.DarkSirenLikelihood(cat)
+    c.set_option("lambda_tile", 4)
+    c.autotune(16, grad=True, cache_path=str(cache))
+    assert len(cache.read_text().splitlines()) == 2
+    assert c.info("lambda_tile") == 4
+    c.close()
+    a.close()

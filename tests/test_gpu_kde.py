@@ -57,7 +57,7 @@ def test_config1_kde(env, precision, bandwidth):
 
 
 @pytest.mark.parametrize("bandwidth", BANDWIDTHS)
-@pytest.mark.parametrize("gate_mode", [0, 2])
+@pytest.mark.parametrize("gate_mode", [0, 1, 2])
 def test_ragged_pixels_kde(env, bandwidth, gate_mode):
     """Pixels of 0, 1, 2, 3, 7, 63, 64, 65, 130 and 200 samples: one-chunk and
     multi-chunk passes, zero bandwidths (single samples, without the gate)."""
@@ -68,6 +68,30 @@ def test_ragged_pixels_kde(env, bandwidth, gate_mode):
     lam[0] = synth.fiducial_lambda()
     r = _run(env, cat, lam, kde_bandwidth=bandwidth, gate_mode=gate_mode)
     _check(env, cat, lam, r, TOL_LOGL_FP32, bandwidth=bandwidth, gate_mode=gate_mode)
+
+
+def test_ragged_pixels_kde_fp64(env):
+    """FP64 tiles of four points over ragged pixels: nine points, three tiles,
+    the last holding one point."""
+    synth = env["synth"]
+    log("[kde ragged fp64 biweight]")
+    cat = ragged_catalog(synth, RAGGED)
+    lam = synth.draw_lambdas(9, seed=47)
+    lam[0] = synth.fiducial_lambda()
+    r = _run(env, cat, lam, "fp64", kde_bandwidth="biweight", gate_mode=2)
+    _check(env, cat, lam, r, TOL_LOGL_FP64, bandwidth="biweight", gate_mode=2)
+
+
+def test_downsampled_kde(env):
+    """At most 40 samples per pixel kept at upload: the bandwidths and grids
+    come from the kept samples (their d_L order is rebuilt after the cut)."""
+    O, synth = env["O"], env["synth"]
+    log("[kde downsampled 40/pixel]")
+    ds = O.downsample(env["c1"], 40, seed=5)
+    lam = synth.draw_lambdas(3, seed=53)
+    lam[0] = synth.fiducial_lambda()
+    r = _run(env, env["c1"], lam, max_samples_per_pixel=40, downsample_seed=5, gate_mode=2)
+    _check(env, ds, lam, r, TOL_LOGL_FP32, gate_mode=2)
 
 
 @pytest.mark.parametrize("n_grid", [2, 64, 300, 1024])
