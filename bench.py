@@ -32,10 +32,14 @@ sys.path.insert(0, ROOT)
 # window, smoothing, exponent bookkeeping).
 FLOP_PER_WEIGHT_FWD = 175
 FLOP_PER_WEIGHT_GRAD = 300
-# KDE numerator: the weight without prior and rate (164, from the source), and
-# per (sample, grid node) kernel term: difference, square, exp2, multiply-add (5).
+# KDE numerator: the weight without prior and rate (164, from the source); per
+# (sample, grid node) kernel term: difference, square, exp2, multiply-add (5); per
+# grid node of a (pixel, point) pair: position and trapezoid weight (3), prior
+# interpolation (5), rate psi(z)/(1+z) (1+z, log2, two exponents, two exp2, sum,
+# reciprocal: 9), products and scaled coordinate (3), the node's dot-product term (2).
 FLOP_PER_KDE_WEIGHT = 164
 FLOP_PER_KDE_NODE = 5
+FLOP_PER_KDE_GRID_NODE = 22
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6
@@ -206,8 +210,10 @@ def main():
     achieved = flops / (sweep_avg * 1e-3) / 1e12
     if kde:
         kde_evals = lik.info("kde_evals")
+        kde_nodes = lik.info("kde_nodes")
         kde_avg = float(np.mean(pix_ms))
-        flops = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kde_evals
+        flops = (FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kde_evals
+                 + FLOP_PER_KDE_GRID_NODE * kde_nodes)
         achieved = flops / (kde_avg * 1e-3) / 1e12
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
     traffic = None
@@ -223,7 +229,9 @@ def main():
                 "kernel_ms": round(kde_avg if kde else sweep_avg, 4),
                 "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
                 **({"flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE,
-                    "kde_node_evals_per_launch": kde_evals, "kde_weights_per_launch": cat.n_samp * B}
+                    "flop_per_kde_grid_node": FLOP_PER_KDE_GRID_NODE,
+                    "kde_node_evals_per_launch": kde_evals, "kde_grid_nodes_per_launch": kde_nodes,
+                    "kde_weights_per_launch": cat.n_samp * B}
                    if kde else {"flop_per_weight": F, "weights_per_launch": n_w * B}),
                 "chunk": int(lik.info("chunk")), "items": int(lik.info("n_items"))}
 
@@ -294,8 +302,9 @@ def main():
         torch.cuda.synchronize()
         lik.set_option("timing", 0)
         kev = lik.info("kde_evals")
+        knodes = lik.info("kde_nodes")
         kavg = float(np.mean(kms))
-        kfl = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kev
+        kfl = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kev + FLOP_PER_KDE_GRID_NODE * knodes
         kach = kfl / (kavg * 1e-3) / 1e12
         kde_side = {"metric": "Lambda-evaluations/sec (log L, KDE numerator (%s), %d-node grid)"
                               % (args.kde_bandwidth, int(lik.info("kde_grid"))),
@@ -306,7 +315,9 @@ def main():
                                  "unit": "TFLOP/s", "frac": round(kach / PEAK_FP32_VECTOR_TFLOPS, 4),
                                  "traffic": None, "kernel": "kde_kernel<float,64> + kde_event_kernel",
                                  "kernel_ms": round(kavg, 3), "kde_node_evals_per_launch": kev,
-                                 "flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE}}
+                                 "kde_grid_nodes_per_launch": knodes,
+                                 "flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE,
+                                 "flop_per_kde_grid_node": FLOP_PER_KDE_GRID_NODE}}
         lik.set_option("numerator", 0)
 
     cpu = None

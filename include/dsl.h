@@ -163,7 +163,10 @@ int dsl_set_option(dsl_handle* h, const char* key, double value);
 
 /* Read back an option or a catalogue size ("n_events", "n_pix", "n_samp",
  * "n_inj", "n_items", "precision", ...), "lambda_tile_used" (the Lambda tile
- * of the last call), "device_bytes" (device memory the handle holds), or, after a call made with option
+ * of the last call), "device_bytes" (device memory the handle holds),
+ * "kde_evals" and "kde_nodes" (of the last call with the KDE numerator: the
+ * (sample, grid node) kernel terms and the grid nodes evaluated; both wait for
+ * the device), or, after a call made with option
  * "timing" = 1, "ms_sweep_only" (the weight sweep alone) and "ms_pixels" (the
  * per-pixel stage after it: the KDE kernel, or the gate of split pixels).
  * Returns DSL_EINVAL for unknown keys. */

@@ -434,7 +434,7 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
     return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
   if ((e = h->cpart.ensure(sizeof(double) * NF_CSLICE * (size_t)B * combine_slices(h, B))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (combine slices)");
-  if (h->numerator == 1 && (e = h->kde_evals.ensure(sizeof(unsigned long long))) != hipSuccess)
+  if (h->numerator == 1 && (e = h->kde_evals.ensure(2 * sizeof(unsigned long long))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE counter)");
   if (h->numerator == 1 &&
       (e = h->kde_ev.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_events, 1))) != hipSuccess)
@@ -849,13 +849,15 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
   else if (k == "n_cu") *v = h->n_cu;
   else if (k == "lambda_tile_used") *v = h->last_gl;
-  else if (k == "kde_evals") {
-    // (sample, grid node) kernel evaluations of the last KDE call (waits for the device)
+  else if (k == "kde_evals" || k == "kde_nodes") {
+    // of the last KDE call (waits for the device): (sample, grid node) kernel
+    // terms, and grid nodes (each a prior and rate evaluation) over all
+    // (pixel, point) pairs with a bandwidth > 0
     if (!h->kde_evals.p) return fail(DSL_ESTATE, "no KDE call yet");
-    unsigned long long n = 0;
+    unsigned long long n[2] = {0, 0};
     HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(&n, h->kde_evals.p, sizeof(n), hipMemcpyDeviceToHost));
-    *v = (double)n;
+    HIPCHK(hipMemcpy(n, h->kde_evals.p, sizeof(n), hipMemcpyDeviceToHost));
+    *v = (double)n[k == "kde_nodes" ? 1 : 0];
   } else if (k == "ms_sweep_only" || k == "ms_pixels") {
     // of the last timed call: the sweep alone, and the per-pixel stage after it
     // (KDE kernel, or the gate of split pixels)

@@ -142,7 +142,7 @@ struct KdeArgs {
   double neff_min;
   int32_t gate_mode;
   double* out;               // [B][n_pix][NF_KDE]
-  unsigned long long* evals; // (sample, node) kernel evaluations of the launch (zeroed before it)
+  unsigned long long* evals; // [0] (sample, node) kernel terms, [1] grid nodes of the launch (zeroed before it)
 };
 
 struct GateSplitArgs {

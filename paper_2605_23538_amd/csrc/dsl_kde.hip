@@ -140,7 +140,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
   const int ng = (nl + 3) >> 2;   // groups of four points in this tile
   const int64_t n_tasks = a.n_pix * ng;
-  unsigned long long evals = 0;   // kept by the first lane of each row
+  unsigned long long evals = 0, nodes = 0;   // kept by the first lane of each row
   for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
     const int64_t p = t / ng;
     const int l = 4 * (int)(t - p * ng) + q;   // this row's point in the tile
@@ -286,20 +286,34 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const double dz = (gb - ga) / (double)(a.n_grid - 1);
       // coordinates scaled by sqrt(log2(e)/2)/h, so each term is exp2(-(x_g - x_k)^2)
       const T invh = (T)(sqrt(0.5 * LOG2E) / h);
+      // psi(z)/(1+z) = 1 / (2^(-(gamma-1) L) + 2^((kappa+1) L - (gamma+kappa) L_p)), L = log2(1+z)
+      const T ra = -(c.gm3 + (T)2), rb = c.gk - (c.gm3 + (T)2), rc = -c.gk * c.Lp;
+      const unsigned nz2 = (unsigned)(a.n_z - 2);
+      const double dz16 = 16.0 * dz;
+      if (kl == 0) nodes += (unsigned long long)a.n_grid;
       for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
         T zgs[NB], vg[NB];
+        // Node g = g0 + kl + 16 i.  Trapezoid weight min(max(n_grid - 1/2 - g, 0), 1):
+        // 1 inside, 1/2 at the last node, 0 past the end (the first node is halved below).
+        double zd = ga + (double)(g0 + kl) * dz;
+        const T cw = (T)a.n_grid - (T)0.5 - (T)(g0 + kl);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-          const int g = g0 + kl + 16 * i;
-          zgs[i] = (T)0;
-          vg[i] = (T)0;
-          if (g < a.n_grid) {
-            const T zg = (T)fmin(ga + (double)g * dz, a.z_max);
-            const T cg = (g == 0 || g == a.n_grid - 1) ? (T)0.5 : (T)1;
-            zgs[i] = zg * invh;
-            vg[i] = cg * los_at<T>(row, a.n_z, inv_dz, zg) * rate_at<T>(c, zg);
-          }
+          const T zg = (T)fmin(zd, a.z_max);
+          zd += dz16;
+          const T cg = fmin(fmax(cw - (T)(16 * i), (T)0), (T)1);
+          const T x = zg * inv_dz;   // zg >= 0
+          unsigned k = (unsigned)x;
+          k = k < nz2 ? k : nz2;
+          const T f = x - (T)k;
+          const float* rk = row + k;
+          const T l0 = (T)rk[0], l1 = (T)rk[1];
+          const T L = Mth<T>::log2((T)1 + zg);
+          const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
+          vg[i] = cg * rate * (l0 + f * (l1 - l0));
+          zgs[i] = zg * invh;
         }
+        if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
         for (int c0 = 0; c0 < n; c0 += 16) {
           T z, w;
           z_w(c0, z, w);
@@ -313,19 +327,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
 #pragma unroll
           for (int i = 0; i < NB; ++i) accf[i] = (T)0;
           // zero weights (out of support) add exact zeros: no per-sample branch
-          for (int j = 0; j < cnt; ++j) {
+          int j = 0;
+          do {   // cnt >= 1
             const T wj = __shfl(w, j, 16);
             const T zj = __shfl(zsc, j, 16);
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-              const T x = zgs[i] - zj;
-              accf[i] = fma(wj, Mth<T>::exp2(-(x * x)), accf[i]);
+              const T xx = zgs[i] - zj;
+              accf[i] = fma(wj, Mth<T>::exp2(-(xx * xx)), accf[i]);
             }
-          }
-          double part = 0.0;
+          } while (++j < cnt);
+          // the lane's 16 positive terms of this chunk in T, the running sum in FP64
+          T part = (T)0;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) part += (double)vg[i] * (double)accf[i];
-          Tt += part;
+          for (int i = 0; i < NB; ++i) part = fma(vg[i], accf[i], part);
+          Tt += (double)part;
         }
       }
       Tt = row_reduce(Tt, [](double x, double y) { return x + y; }) * dz / (h * 2.5066282746310002);
@@ -337,10 +353,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       out[3] = pass ? S2 : 0.0;
     }
   }
-  if (a.evals && kl == 0 && evals) atomicAdd(a.evals, evals);
+  if (a.evals && kl == 0) {
+    if (evals) atomicAdd(a.evals, evals);
+    if (nodes) atomicAdd(a.evals + 1, nodes);
+  }
 }
 
-__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
 
 // Per (event, point): merge the event's pixel records {R, T, S1, S2} (pixels
 // with S1 > 0, i.e. passing the gate) under one exponent.  One wavefront per
@@ -418,7 +439,7 @@ static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
 
 hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st) {
   if (a.evals) {
-    zero_u64_kernel<<<1, 64, 0, st>>>(a.evals);
+    zero_u64_kernel<<<1, 64, 0, st>>>(a.evals, 2);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

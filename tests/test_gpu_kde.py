@@ -156,3 +156,36 @@ def test_kde_deterministic_and_graph_replay(env):
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
     lik.close()
+
+
+def test_kde_work_counters(env):
+    """Grid-node counter = (pixel, point) pairs with a bandwidth > 0 (counted
+    with the oracle's weights and bandwidth rule, no gate) x grid nodes; the
+    kernel-term counter is a multiple of the grid size bounded by samples x
+    points x nodes."""
+    import torch as T_
+    torch, synth, O = env["torch"], env["synth"], env["O"]
+    cat = env["c1"]
+    B, n_grid = 5, 256
+    lam1 = synth.fiducial_lambda()
+    L = O.Lam.of(T_.tensor(lam1, dtype=T_.float64))
+    n_h = 0
+    for j in range(len(cat.pix_samp_off) - 1):
+        s0, s1 = int(cat.pix_samp_off[j]), int(cat.pix_samp_off[j + 1])
+        if s1 == s0:
+            continue
+        t = lambda a: T_.from_numpy(np.ascontiguousarray(a[s0:s1], dtype=np.float64))
+        z, inside, lw = O.kde_log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), cat.z_max, L)
+        z, lw = z[inside], lw[inside]
+        if z.numel() and math.isfinite(float(O.lse_all(lw))) and float(O.BANDWIDTHS["scott"](z)) > 0:
+            n_h += 1
+    lam = torch.tensor(lam1[None].repeat(B, 0), device="cuda")
+    lik = env["binding"].DarkSirenLikelihood(cat, numerator="kde", gate_mode=2)
+    r = lik.loglike(lam)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(r["logL"].cpu().numpy()))
+    log(f"  {n_h} pixels with a bandwidth, {lik.info('kde_nodes'):.0f} grid nodes")
+    assert n_h > 0 and lik.info("kde_nodes") == n_h * B * n_grid
+    ev = lik.info("kde_evals")
+    assert ev % n_grid == 0 and 0 < ev <= cat.n_samp * B * n_grid
+    lik.close()
