@@ -8,8 +8,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2605_23538_amd", "libdsl.so")
 
-# Relative tolerance on ln L of the FP32-bulk path (spec bound) and of the
-# FP64 path; the FP64 path is held far tighter than the bound it must meet.
+# Relative tolerance on ln L of the FP32-bulk path (the accuracy the method must
+# meet) and of the FP64 path, which is held far tighter than that bound.
 TOL_LOGL_FP32 = 1e-6
 TOL_LOGL_FP64 = 1e-10
 # Gradient: |g - g_ref| <= 1e-4 max(|g_ref|, 1e-2 ||g_ref||) per component.
