@@ -133,3 +133,32 @@ def test_downsampled_catalogue(env):
         check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, TOL_LOGL_FP32)
         check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
     lik.close()
+
+
+@pytest.mark.parametrize("z_prior", ["los", "comoving"])
+def test_adjoint_vs_central_differences(env, z_prior):
+    """The FP64 adjoint at the fiducial point against central differences of
+    the library's own FP64 ln L, all from one launch of 33 points (the point and
+    +-h along each of the 16 entries).  No gate, so ln L is smooth in Lambda
+    apart from support edges."""
+    torch, cat, synth = env["torch"], env["cat"], env["synth"]
+    log(f"[adjoint vs central differences, {z_prior} prior]")
+    lik = env["binding"].DarkSirenLikelihood(cat, precision="fp64", z_prior=z_prior, gate_mode=2)
+    lam0 = synth.fiducial_lambda()
+    hs = 1e-6 * np.maximum(np.abs(lam0), 1.0)
+    pts = [lam0]
+    for p in range(16):
+        for s in (1.0, -1.0):
+            x = lam0.copy()
+            x[p] += s * hs[p]
+            pts.append(x)
+    r = lik.loglike_grad(torch.tensor(np.stack(pts), device="cuda"))
+    torch.cuda.synchronize()
+    lnl = r["logL"].cpu().numpy()
+    g = r["grad"][0].cpu().numpy()
+    assert np.all(np.isfinite(lnl))
+    fd = np.array([(lnl[1 + 2 * p] - lnl[2 + 2 * p]) / (2 * hs[p]) for p in range(16)])
+    gn = np.linalg.norm(g)
+    bad = np.abs(fd - g) > 2e-6 * gn + 1e-5 * np.abs(g)
+    assert not bad.any(), [(synth.LAMBDA_NAMES[p], fd[p], g[p]) for p in np.flatnonzero(bad)]
+    lik.close()
