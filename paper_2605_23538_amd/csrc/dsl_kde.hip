@@ -115,6 +115,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
   constexpr int NB = 16;   // grid nodes per lane per block of 256 nodes
   extern __shared__ __align__(16) unsigned char smem[];
+  // block work counters: (sample, node) kernel terms, grid nodes evaluated
+  __shared__ unsigned long long work[2];
+  if (threadIdx.x < 2) work[threadIdx.x] = 0ull;
   T2* cosL = reinterpret_cast<T2*>(smem);
   T2* winL = cosL + (NU + 1) * LT;
   const int tile = blockIdx.y;
@@ -140,7 +143,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
   const int ng = (nl + 3) >> 2;   // groups of four points in this tile
   const int64_t n_tasks = a.n_pix * ng;
-  unsigned long long evals = 0, nodes = 0;   // kept by the first lane of each row
   for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
     const int64_t p = t / ng;
     const int l = 4 * (int)(t - p * ng) + q;   // this row's point in the tile
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const T ra = -(c.gm3 + (T)2), rb = c.gk - (c.gm3 + (T)2), rc = -c.gk * c.Lp;
       const unsigned nz2 = (unsigned)(a.n_z - 2);
       const double dz16 = 16.0 * dz;
-      if (kl == 0) nodes += (unsigned long long)a.n_grid;
+      if (kl == 0 && a.evals) atomicAdd(&work[1], (unsigned long long)a.n_grid);
       for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
         T zgs[NB], vg[NB];
         // Node g = g0 + kl + 16 i.  Trapezoid weight min(max(n_grid - 1/2 - g, 0), 1):
@@ -321,7 +323,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
           const int cnt = n - c0 < 16 ? n - c0 : 16;
           if (g0 == 0) {
             const unsigned long long m = __ballot(w > (T)0);
-            if (kl == 0) evals += (unsigned long long)__popcll((m >> (16 * q)) & 0xffffull) * a.n_grid;
+            if (kl == 0 && a.evals)
+              atomicAdd(&work[0], (unsigned long long)__popcll((m >> (16 * q)) & 0xffffull) * a.n_grid);
           }
           T accf[NB];
 #pragma unroll
@@ -353,10 +356,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       out[3] = pass ? S2 : 0.0;
     }
   }
-  if (a.evals && kl == 0) {
-    if (evals) atomicAdd(a.evals, evals);
-    if (nodes) atomicAdd(a.evals + 1, nodes);
-  }
+  __syncthreads();
+  if (a.evals && threadIdx.x < 2 && work[threadIdx.x]) atomicAdd(a.evals + threadIdx.x, work[threadIdx.x]);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
