@@ -102,11 +102,31 @@ def cpu_baseline(cat, lam_row, grad, kde=None):
     w_sub = sub.n_samp + sub.n_inj
     w_full = cat.n_samp + cat.n_inj
     per_lambda_s = dt * w_full / w_sub
-    return {"value": 1.0 / per_lambda_s, "unit": "Lambda-evals/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle ({'KDE ln L, ' + kde + ' bandwidth' if kde else 'ln L + autograd gradient' if grad else 'ln L'}) on the first {n_ev} events "
-                      f"({sub.n_samp} samples) and first {n_inj} injections for 1 Lambda: {dt:.2f} s, "
-                      f"scaled by {w_full}/{w_sub} sample-weights to one full-catalogue Lambda"}
+    what = 'KDE ln L, ' + kde + ' bandwidth' if kde else 'ln L + autograd gradient' if grad else 'ln L'
+    res = {"value": 1.0 / per_lambda_s, "unit": "Lambda-evals/s", "cores": torch.get_num_threads(),
+           "kind": "oracle",
+           "sample": f"FP64 oracle ({what}) on the first {n_ev} events "
+                     f"({sub.n_samp} samples) and first {n_inj} injections for 1 Lambda: {dt:.2f} s, "
+                     f"scaled by {w_full}/{w_sub} sample-weights to one full-catalogue Lambda"}
+    # the same oracle on one core, on a smaller sample
+    n_ev1, n_inj1 = (10, 250_000) if kde is None else (2, 250_000)
+    sub1 = cat.subset(np.arange(n_ev1), inj=slice(0, n_inj1))
+    nt = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        if kde is None:
+            O.loglike(sub1, lam_row, grad=grad)
+        else:
+            O.loglike_kde(sub1, lam_row, bandwidth=kde)
+        dt1 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(nt)
+    w_sub1 = sub1.n_samp + sub1.n_inj
+    res["one_core"] = {"value": w_sub1 / (dt1 * w_full), "unit": "Lambda-evals/s", "cores": 1,
+                       "sample": f"first {n_ev1} events ({sub1.n_samp} samples) and first {n_inj1} "
+                                 f"injections: {dt1:.2f} s, scaled by {w_full}/{w_sub1}"}
+    return res
 
 
 def main():
