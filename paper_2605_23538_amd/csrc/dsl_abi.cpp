@@ -279,13 +279,15 @@ int pack_samples(dsl_handle* h, DevBuf& out, const double* m1, const double* m2,
 }
 
 // Default work-item size: about 256 items per compute unit for batched tiles
-// and 64 for one-point tiles (what the autotuner picks on the 33M- and
-// 3.6M-weight catalogues), at least 64 samples.
+// and 64 for one-point tiles, at least 256 samples for batched tiles (each
+// item writes one record per point, which the combine reads back) and 64 for
+// one-point tiles.
 int64_t auto_chunk(const dsl_handle* h, int GL) {
   const int64_t total = h->n_samp + h->n_inj;
   const int64_t per_cu = GL == 1 ? 64 : 256;
+  const int64_t lo = GL == 1 ? 64 : 256;
   int64_t c = total / ((int64_t)h->n_cu * per_cu);
-  return std::max<int64_t>(64, std::min<int64_t>(16384, c));
+  return std::max<int64_t>(lo, std::min<int64_t>(16384, c));
 }
 
 // Work list: runs of whole pixels of one event (about `chunk` samples each; a
@@ -372,12 +374,19 @@ int build_items(dsl_handle* h, int64_t chunk) {
   return DSL_OK;
 }
 
+// Default Lambda tile: the largest the batch fills (64 from 48 points, 16 from
+// 12, 4 from 3) that still leaves at least 128 work units (item x tile) per
+// compute unit; small catalogues take narrow tiles so that every CU has work.
 int default_gl(const dsl_handle* h, int B) {
   if (!h->fp32) return B >= 4 ? 4 : 1;
-  if (B >= 48) return 64;
-  if (B >= 12) return 16;
-  if (B >= 3) return 4;
-  return 1;
+  const int cap = B >= 48 ? 64 : (B >= 12 ? 16 : (B >= 3 ? 4 : 1));
+  const int64_t total = h->n_samp + h->n_inj;
+  for (int gl = cap; gl > 4; gl /= 4) {
+    const int64_t chunk = auto_chunk(h, gl);
+    const int64_t units = ((total + chunk - 1) / chunk) * ((B + gl - 1) / gl);
+    if (units >= 128 * (int64_t)h->n_cu) return gl;
+  }
+  return cap < 4 ? cap : 4;
 }
 
 // Workgroup shape of the sweep. The FP32 adjoint fits 3 waves per SIMD (<= 168
