@@ -109,7 +109,10 @@ __device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
 template <typename T> struct KdeWaves { static constexpr int W = 4; };
 template <> struct KdeWaves<double> { static constexpr int W = 2; };
 
-template <typename T, int LT>
+// ROWPIX (batches of fewer than four points): the four rows of a wavefront take
+// four consecutive (pixel, point) pairs, pixel-major, instead of four points of
+// one pixel, so no row idles; pixel bounds and loop counts are then per row.
+template <typename T, int LT, bool ROWPIX>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>::W))) void kde_kernel(KdeArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
@@ -142,17 +145,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
   const TabView<T> tv{cosL, winL, nullptr};
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
   const int ng = (nl + 3) >> 2;   // groups of four points in this tile
-  const int64_t n_tasks = a.n_pix * ng;
+  const int64_t n_pairs = a.n_pix * nl;
+  const int64_t n_tasks = ROWPIX ? (n_pairs + 3) / 4 : a.n_pix * ng;
   for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
-    const int64_t p = t / ng;
-    const int l = 4 * (int)(t - p * ng) + q;   // this row's point in the tile
-    const bool act = l < nl;
+    int64_t p;
+    int l;   // this row's pixel and point in the tile
+    bool act;
+    if constexpr (ROWPIX) {
+      const int64_t i = 4 * t + q;
+      act = i < n_pairs;
+      p = act ? i / nl : 0;
+      l = act ? (int)(i - p * nl) : 0;
+    } else {
+      p = t / ng;
+      l = 4 * (int)(t - p * ng) + q;
+      act = l < nl;
+    }
     const int b = tile * LT + (act ? l : 0);
     const LamC<T> c = lamc[b];
     const bool live = act && c.valid;
     double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
     const int64_t s0 = a.pix_off[p];
-    const int n = (int)(a.pix_off[p + 1] - s0);
+    const int n = ROWPIX && !act ? 0 : (int)(a.pix_off[p + 1] - s0);
     // ---- pass A
     PixAcc<false, T> pa;
     pa.zero();
@@ -419,9 +433,9 @@ static size_t kde_lds_bytes() {
   return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
 }
 
-template <typename T>
+template <typename T, bool ROWPIX>
 static hipError_t kde_attr() {
-  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT>,
+  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, ROWPIX>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
 }
 
@@ -429,12 +443,14 @@ template <typename T>
 static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
   constexpr int LT = KdeTile<T>::LT;
   const int n_tiles = (a.B + LT - 1) / LT;
-  const int64_t tasks = a.n_pix * ((a.B < LT ? a.B : LT) + 3) / 4;
+  const bool rowpix = a.B < 4;   // fewer points than rows: rows take pixels
+  const int64_t tasks = rowpix ? (a.n_pix * a.B + 3) / 4 : a.n_pix * (((a.B < LT ? a.B : LT) + 3) / 4);
   int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
   if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
   if (grid_x < 1) grid_x = 1;
   if (a.n_grid < 2 || a.n_grid > KDE_GRID_MAX) return hipErrorInvalidValue;
-  kde_kernel<T, LT><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
+  if (rowpix) kde_kernel<T, LT, true><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
+  else kde_kernel<T, LT, false><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
   return hipGetLastError();
 }
 
@@ -458,8 +474,10 @@ hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64
 // Raise the dynamic-LDS limit of every KDE variant (once, outside any capture).
 hipError_t init_kde_attrs() {
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = kde_attr<float>();
-  if (e == hipSuccess) e = kde_attr<double>();
+  if (e == hipSuccess) e = kde_attr<float, false>();
+  if (e == hipSuccess) e = kde_attr<float, true>();
+  if (e == hipSuccess) e = kde_attr<double, false>();
+  if (e == hipSuccess) e = kde_attr<double, true>();
   return e;
 }
 

@@ -94,6 +94,24 @@ def test_downsampled_kde(env):
     _check(env, ds, lam, r, TOL_LOGL_FP32, gate_mode=2)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("B", [1, 2, 3])
+@pytest.mark.parametrize("bandwidth", ["scott", "biweight"])
+def test_fewer_points_than_rows(env, precision, B, bandwidth):
+    """Batches of 1-3 points: the rows of a wavefront take different pixels of
+    the ragged catalogue (0 to 200 samples side by side), with and without the
+    gate."""
+    synth = env["synth"]
+    log(f"[kde B={B} {precision} {bandwidth}]")
+    cat = ragged_catalog(synth, RAGGED)
+    lam = synth.draw_lambdas(B, seed=59)
+    lam[0] = synth.fiducial_lambda()
+    tol = TOL_LOGL_FP32 if precision == "fp32" else TOL_LOGL_FP64
+    for gate in (0, 2):
+        r = _run(env, cat, lam, precision, kde_bandwidth=bandwidth, gate_mode=gate)
+        _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
+
+
 @pytest.mark.parametrize("n_grid", [2, 64, 300, 1024])
 def test_grid_sizes(env, n_grid):
     """Grids below, at and above one node per lane, up to 16 nodes per lane."""
