@@ -115,7 +115,7 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals, cpart;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals, cpart, ev_rec;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -423,6 +423,12 @@ int combine_slices(const dsl_handle* h, int B) {
   return std::max(1, std::min(32, std::min(by_items, by_cu)));
 }
 
+// Events spanning many work items (the monte-carlo numerator) are merged by one
+// wavefront each before the combine, instead of one thread walking the items.
+bool merge_events(const dsl_handle* h) {
+  return h->numerator == 0 && h->n_events > 0 && h->inj_slot0 >= 16 * h->n_events;
+}
+
 int ensure_workspace(dsl_handle* h, int B, bool grad) {
   const int NU = h->fp32 ? NU_F32 : NU_F64, NW = h->fp32 ? NW_F32 : NW_F64;
   const size_t t1 = h->fp32 ? sizeof(float) : sizeof(double);
@@ -443,6 +449,8 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
     return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
   if ((e = h->cpart.ensure(sizeof(double) * NF_CSLICE * (size_t)B * combine_slices(h, B))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (combine slices)");
+  if (merge_events(h) && (e = h->ev_rec.ensure(sizeof(double) * nf * (size_t)B * h->n_events)) != hipSuccess)
+    return fail(DSL_ENOMEM, "workspace (event records)");
   if (h->numerator == 1 && (e = h->kde_evals.ensure(2 * sizeof(unsigned long long))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE counter)");
   if (h->numerator == 1 &&
@@ -555,6 +563,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.grad = o.grad;
   c.gmap = h->gmap.as<double>();
   c.kde = h->numerator == 1 ? h->kde_ev.as<double>() : nullptr;
+  c.ev_rec = merge_events(h) ? h->ev_rec.as<double>() : nullptr;
   c.n_slices = combine_slices(h, B);
   c.cpart = h->cpart.as<double>();
   HIPCHK(launch_combine(grad, c, st));
@@ -581,7 +590,8 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   // captured graphs hold workspace addresses: drop them all when any buffer moved
   const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
-                                        h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p};
+                                        h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
+                                        h->ev_rec.p};
   if (sig != h->ws_sig) {
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
@@ -880,7 +890,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "device_bytes") {
     *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
                   h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_pix_off.n +
-                  h->kde_out.n + h->kde_ev.n);
+                  h->kde_out.n + h->kde_ev.n + h->ev_rec.n + h->cpart.n);
   } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
   return DSL_OK;
 }

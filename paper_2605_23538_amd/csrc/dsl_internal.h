@@ -181,6 +181,7 @@ struct CombineArgs {
   double* grad;                 // [B][16] or null
   const double* gmap;           // [B][N_GMAP] (adjoint only)
   const double* kde;            // [B][n_events][NF_KDE] event records (KDE numerator) or null
+  double* ev_rec;               // [B][n_events][nf] per-event merged item records, or null
   int32_t n_slices;             // workgroups per point (events and injection slots strided over them)
   double* cpart;                // [B][n_slices][NF_CSLICE] slice records when n_slices > 1
 };

@@ -65,10 +65,11 @@ __device__ inline double log_dPhi(double mu, double sig, double lo, double hi) {
 }
 
 // ---------------------------------------------------------------------------
-// setup: per-Lambda constants and tables (FP64), one workgroup per point
+// setup: per-Lambda constants and tables (FP64), two workgroups per point
 // ---------------------------------------------------------------------------
+constexpr int SETUP_THREADS = 1024;
 template <typename T>
-__global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ lam, int B, double z_max,
+__global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __restrict__ lam, int B, double z_max,
                                                     LamC<T>* __restrict__ lamc,
                                                     typename V2<T>::t* __restrict__ cos_tab,
                                                     typename V2<T>::t* __restrict__ win_tab,
@@ -195,48 +196,66 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
     }
     return;
   }
-  // --- smoothing-window integrals on NW panels (Gauss-Legendre 8 x 2 per panel)
-  // panel integrals of m^beta S, and of m^beta d S/d(beta, m_min, dm) for the adjoint.
+  // --- truncated-Gaussian normalisers of the two peaks and their derivatives
+  // (-ln dPhi with respect to mu, sigma, m_min, m_max): one lane each, in the
+  // last wavefront, beside the window integrals.
+  __shared__ double gpk[2][5];
+  const int gl = tid - ((int)blockDim.x - 2);
+  if (gl >= 0) {
+    const double r2pi = 2.5066282746310002;
+    const double mu = gl == 0 ? muL : muH, sg = gl == 0 ? sL : sH;
+    const double ldP = ok ? log_dPhi(mu, sg, mmin, mmax) : 0.0;
+    const double dP = exp(ldP);
+    const double za = (mmin - mu) / sg, zb = (mmax - mu) / sg;
+    const double pa = exp(-0.5 * za * za) / r2pi, pb = exp(-0.5 * zb * zb) / r2pi;
+    gpk[gl][0] = -log(sg * r2pi) - ldP;
+    gpk[gl][1] = -(-pb + pa) / sg / dP;
+    gpk[gl][2] = -1.0 / sg - (-pb * zb + pa * za) / sg / dP;
+    gpk[gl][3] = pa / sg / dP;
+    gpk[gl][4] = -pb / sg / dP;
+  }
+  // --- smoothing-window integrals on NW panels (Gauss-Legendre 8 x 2 per
+  // panel): integrals of m^beta S, and of m^beta d S/d(beta, m_min, dm) for the
+  // adjoint, one quarter panel (four nodes) per thread.
+  __shared__ double qsum[4][4 * NW];
   const bool win = ok && dm > 0;
-  for (int j = tid; j < NW; j += blockDim.x) {
+  for (int i = tid; i < 4 * NW; i += blockDim.x) {
+    const int j = i >> 2, qtr = i & 3;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     if (win) {
       const double ta = (double)j / NW, h = 1.0 / NW;
-      for (int half = 0; half < 2; ++half) {
-        const double c = ta + (half + 0.5) * 0.5 * h;
-        for (int q = 0; q < 8; ++q) {
-          const double t = c + 0.25 * h * GL8_X[q];
-          const double m = mmin + dm * t;
-          const SmoothD sd = smooth_d(m - mmin, dm);
-          const double wq = GL8_W[q] * 0.25 * h * dm;
-          const double mb = exp(beta * log(m));
-          a0 += wq * mb * sd.S;
-          a1 += wq * mb * log(m) * sd.S;
-          a2 += wq * mb * sd.S * (-sd.dlnS_dm);    // dS/dm_min = -dS/dm
-          a3 += wq * mb * sd.S * sd.dlnS_ddm;
-        }
+      const double c = ta + ((qtr >> 1) + 0.5) * 0.5 * h;
+      for (int u = 0; u < 4; ++u) {
+        const int q = 4 * (qtr & 1) + u;
+        const double t = c + 0.25 * h * GL8_X[q];
+        const double m = mmin + dm * t;
+        const SmoothD sd = smooth_d(m - mmin, dm);
+        const double wq = GL8_W[q] * 0.25 * h * dm;
+        const double lm = log(m);
+        const double mb = exp(beta * lm);
+        a0 += wq * mb * sd.S;
+        a1 += wq * mb * lm * sd.S;
+        a2 += wq * mb * sd.S * (-sd.dlnS_dm);    // dS/dm_min = -dS/dm
+        a3 += wq * mb * sd.S * sd.dlnS_ddm;
       }
     }
-    cum[j + 1] = a0;
-    cumg[0][j + 1] = a1;
-    cumg[1][j + 1] = a2;
-    cumg[2][j + 1] = a3;
+    qsum[0][i] = a0;
+    qsum[1][i] = a1;
+    qsum[2][i] = a2;
+    qsum[3][i] = a3;
   }
   __syncthreads();
-  if (tid == 0) {
-    cum[0] = 0;
-    cumg[0][0] = cumg[1][0] = cumg[2][0] = 0;
-    for (int j = 1; j <= NW; ++j) {
-      cum[j] += cum[j - 1];
-      cumg[0][j] += cumg[0][j - 1];
-      cumg[1][j] += cumg[1][j - 1];
-      cumg[2][j] += cumg[2][j - 1];
+  // running sums over the panels (each panel's quarters in order): one lane per array
+  if (tid < 4) {
+    double* dst = tid == 0 ? cum : cumg[tid - 1];
+    const double* src = qsum[tid];
+    double run = 0.0;
+    dst[0] = 0.0;
+    for (int j = 0; j < NW; ++j) {
+      run += (src[4 * j] + src[4 * j + 1]) + (src[4 * j + 2] + src[4 * j + 3]);
+      dst[j + 1] = run;
     }
-    const double Ms = exp(s * log(M));
-    zw_s[0] = win ? cum[NW] / Ms : 0.0;
-    zw_s[1] = win ? cumg[0][NW] / Ms : 0.0;
-    zw_s[2] = win ? cumg[1][NW] / Ms : 0.0;
-    zw_s[3] = win ? cumg[2][NW] / Ms : 0.0;
+    zw_s[tid] = win ? run / exp(s * log(M)) : 0.0;
   }
   __syncthreads();
   // rho(t) = Z / (S m^s) and its t-derivative; gradient tables d rho / d(beta, m_min, dm).
@@ -284,7 +303,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
   }
 
   if (tid == 0) {
-    const double r2pi = 2.5066282746310002;
     double lnbP, dbPa, dbPmin, dbPmax;
     if (fabs(alpha - 1.0) < 1e-10) {
       const double lr = log(mmax / mmin);
@@ -301,21 +319,9 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ l
       dbPmin = a1 * Bm / mmin / (A - Bm);
       dbPmax = -a1 * A / mmax / (A - Bm);
     }
-    const double lnbL = -log(sL * r2pi) - (ok ? log_dPhi(muL, sL, mmin, mmax) : 0.0);
-    const double lnbH = -log(sH * r2pi) - (ok ? log_dPhi(muH, sH, mmin, mmax) : 0.0);
-    // derivatives of -ln dPhi with respect to mu, sigma, mmin, mmax
-    auto dnorm = [&](double mu, double sg, double& dmu, double& dsg, double& dlo, double& dhi) {
-      const double a = (mmin - mu) / sg, bb = (mmax - mu) / sg;
-      const double dP = exp(ok ? log_dPhi(mu, sg, mmin, mmax) : 0.0);
-      const double pa = exp(-0.5 * a * a) / r2pi, pb = exp(-0.5 * bb * bb) / r2pi;
-      dmu = -(-pb + pa) / sg / dP;
-      dsg = -1.0 / sg - (-pb * bb + pa * a) / sg / dP;
-      dlo = pa / sg / dP;
-      dhi = -pb / sg / dP;
-    };
-    double dLmu, dLsg, dLlo, dLhi, dHmu, dHsg, dHlo, dHhi;
-    dnorm(muL, sL, dLmu, dLsg, dLlo, dLhi);
-    dnorm(muH, sH, dHmu, dHsg, dHlo, dHhi);
+    const double lnbL = gpk[0][0], lnbH = gpk[1][0];
+    const double dLmu = gpk[0][1], dLsg = gpk[0][2], dLlo = gpk[0][3], dLhi = gpk[0][4];
+    const double dHmu = gpk[1][1], dHsg = gpk[1][2], dHlo = gpk[1][3], dHhi = gpk[1][4];
     const double l2 = LOG2E;
     c.alpha = (T)alpha;
     c.beta = (T)beta;
@@ -695,9 +701,69 @@ __device__ void combine_finish(const CombineArgs& a, int b, double acc, double n
   }
 }
 
-template <bool GRAD, bool KDE = false>
+// Per (event, point): merge the event's item records with one wavefront (lanes
+// stride over the items, then a fixed xor butterfly whose merges are exact
+// power-of-two rescalings and commutative sums, so every lane ends with the
+// same bits); the result, in the item layout, goes to ev_rec.  Used when events
+// span many items, where one thread per event would walk them serially.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void event_merge_kernel(CombineArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= (int64_t)a.n_events * a.B) return;   // whole wavefronts
+  const int b = (int)(w / a.n_events), e = (int)(w % a.n_events);
+  const double* P = a.part + (size_t)b * a.n_items * a.nf;
+  Part3 m{0, 0, 0};
+  double G[GRAD ? 16 : 1];
+#pragma unroll
+  for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+  double Rg = -1e300;
+  for (int sl = a.ev_item_off[e] + lane; sl < a.ev_item_off[e + 1]; sl += 64) {
+    const double* r = P + (size_t)sl * a.nf;
+    const Part3 x{r[0], r[1], r[2]};
+    if constexpr (GRAD) {
+      if (x.S1 > 0) {
+        if (x.R > Rg) {
+          for (int p = 0; p < 16; ++p) G[p] = (Rg > -1e299) ? ldexp(G[p], (int)(Rg - x.R)) : 0.0;
+          Rg = x.R;
+        }
+        for (int p = 0; p < 16; ++p) G[p] += ldexp(r[4 + p], (int)(x.R - Rg));
+      }
+    }
+    m = pmerge(m, x);
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Part3 o{__shfl_xor(m.R, off), __shfl_xor(m.S1, off), __shfl_xor(m.S2, off)};
+    m = pmerge(m, o);
+    if constexpr (GRAD) {
+      const double Ro = __shfl_xor(Rg, off);
+      const double Rm = fmax(Rg, Ro);
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const double go = __shfl_xor(G[p], off);
+        G[p] = ((Rg > -1e299) ? ldexp(G[p], (int)(Rg - Rm)) : 0.0) + ((Ro > -1e299) ? ldexp(go, (int)(Ro - Rm)) : 0.0);
+      }
+      Rg = Rm;
+    }
+  }
+  if (lane == 0) {
+    double* o = a.ev_rec + ((size_t)b * a.n_events + e) * a.nf;
+    o[0] = m.R;
+    o[1] = m.S1;
+    o[2] = m.S2;
+    o[3] = 0.0;
+    if constexpr (GRAD) {
+      for (int p = 0; p < 16; ++p) o[4 + p] = G[p];
+    }
+  }
+}
+
+// PRE: each event's items were merged by event_merge_kernel into one record.
+template <bool GRAD, bool KDE = false, bool PRE = false>
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   static_assert(!(GRAD && KDE), "the KDE numerator has no adjoint");
+  static_assert(!(KDE && PRE), "the KDE numerator has its own event records");
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const double ln2 = LN2;
@@ -727,16 +793,20 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
       num = Part3{r[0], r[1], 0.0};
       m = Part3{r[0], r[2], r[3]};
     }
+    const double* EP = PRE ? a.ev_rec + ((size_t)b * a.n_events + e) * a.nf : nullptr;
+    auto ate = [&](int sl, int f) { return PRE ? EP[f] : at(sl, f); };
+    const int sl0 = (KDE || PRE) ? 0 : a.ev_item_off[e];
+    const int sl1 = KDE ? 0 : (PRE ? 1 : a.ev_item_off[e + 1]);
 #pragma unroll 4
-    for (int sl = KDE ? 0 : a.ev_item_off[e]; sl < (KDE ? 0 : a.ev_item_off[e + 1]); ++sl) {
-      Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
+    for (int sl = sl0; sl < sl1; ++sl) {
+      Part3 x{ate(sl, 0), ate(sl, 1), ate(sl, 2)};
       if constexpr (GRAD) {
         if (x.S1 > 0) {
           if (x.R > Rg) {
             for (int p = 0; p < 16; ++p) G[p] = (Rg > -1e299) ? ldexp(G[p], (int)(Rg - x.R)) : 0.0;
             Rg = x.R;
           }
-          for (int p = 0; p < 16; ++p) G[p] += ldexp(at(sl, 4 + p), (int)(x.R - Rg));
+          for (int p = 0; p < 16; ++p) G[p] += ldexp(ate(sl, 4 + p), (int)(x.R - Rg));
         }
       }
       m = pmerge(m, x);
@@ -936,10 +1006,10 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
                         void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st) {
   if (fp32)
-    setup_kernel<float><<<dim3(B, 2), 256, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
+    setup_kernel<float><<<dim3(B, 2), SETUP_THREADS, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
                                             (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
   else
-    setup_kernel<double><<<dim3(B, 2), 256, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
+    setup_kernel<double><<<dim3(B, 2), SETUP_THREADS, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
                                              (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
   return hipGetLastError();
 }
@@ -1006,9 +1076,22 @@ hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
   const dim3 grid(a.B, a.n_slices);
-  if (a.kde) combine_kernel<false, true><<<grid, 256, 0, st>>>(a);
-  else if (grad) combine_kernel<true><<<grid, 256, 0, st>>>(a);
-  else combine_kernel<false><<<grid, 256, 0, st>>>(a);
+  if (a.kde) {
+    combine_kernel<false, true><<<grid, 256, 0, st>>>(a);
+  } else if (a.ev_rec) {
+    const int64_t threads = (int64_t)a.n_events * a.B * 64;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    if (grad) event_merge_kernel<true><<<blocks, 256, 0, st>>>(a);
+    else event_merge_kernel<false><<<blocks, 256, 0, st>>>(a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (grad) combine_kernel<true, false, true><<<grid, 256, 0, st>>>(a);
+    else combine_kernel<false, false, true><<<grid, 256, 0, st>>>(a);
+  } else if (grad) {
+    combine_kernel<true><<<grid, 256, 0, st>>>(a);
+  } else {
+    combine_kernel<false><<<grid, 256, 0, st>>>(a);
+  }
   if (a.n_slices > 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

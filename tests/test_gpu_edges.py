@@ -238,3 +238,30 @@ def test_autotune_and_cache(mods, tmp_path):
     assert c.info("lambda_tile") == 4
     c.close()
     a.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_event_merge_paths(mods, precision):
+    """Events spanning many work items are merged by one wavefront each before
+    the combine (16-sample items: about 125 items per event); a few large items
+    per event take the serial merge.  Both against the oracle, with gradient."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    lam = synth.draw_lambdas(5, seed=61)
+    lam[0] = synth.fiducial_lambda()
+    refs = [O.loglike(cat, lam[b], grad=True, margins=True) for b in range(len(lam))]
+    tol = TOL_LOGL_FP32 if precision == "fp32" else 1e-10
+    for chunk in (16, 4096):
+        log(f"  [{precision} chunk {chunk}]")
+        lik = mods["binding"].DarkSirenLikelihood(cat, precision=precision)
+        lik.set_option("lambda_tile", 4)
+        lik.set_option("chunk", chunk)
+        r = lik.loglike_grad(torch.tensor(lam, device="cuda"), per_event=True)
+        torch.cuda.synchronize()
+        for b, ref in enumerate(refs):
+            assert int(r["flags"][b]) == ref["flags"]
+            check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, tol)
+            if not ref["flags"]:
+                assert rel_close(float(r["logL"][b]), ref["logL"], tol)
+                check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
+        lik.close()
