@@ -411,7 +411,9 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
     lE2 = segment_lse(lS2p, ev_seg, nE) if n_p else torch.full((nE,), -math.inf, dtype=DT)
     n_s = torch.from_numpy((s_hi - s_lo).astype(np.float64))
     ns_ev = torch.zeros(nE, dtype=DT).index_add(0, ev_seg, n_s) if n_p else torch.zeros(nE, dtype=DT)
-    lnL = lE1 - torch.log(ns_ev)
+    # An event without samples has an empty sum: L_i = 0 (the 1/N_s,i of Eq. 5
+    # is read as 1/max(N_s,i, 1), as in loglike_kde).
+    lnL = lE1 - torch.log(torch.clamp(ns_ev, min=1.0))
     neff_ev = torch.exp(2.0 * lE1.detach() - lE2.detach())
     neff_ev = torch.where(torch.isfinite(lE1.detach()), neff_ev, torch.zeros_like(neff_ev))
     if opt.gate_mode == 1:

@@ -413,6 +413,30 @@ def test_invalid_lambda_and_no_pixel_flags():
     assert r["flags"] & O.FLAG_EVENT_NO_PIXEL and r["logL"] == -math.inf
 
 
+def test_event_without_samples():
+    """An event with no pixels, or with pixels holding no samples, has an empty
+    Monte Carlo sum: ln L_i = -inf (not 0/0), flag 2, in both numerators; the
+    other events keep exactly the values they have without it."""
+    cat = F.tiny_catalog()
+    lam = synth.fiducial_lambda()
+    ref = O.loglike(cat, lam)
+    ref_kde = O.loglike_kde(cat, lam)
+    epo = np.asarray(cat.event_pix_off, np.int64)
+    # event 0 without pixels, in front of the others
+    no_pix = synth.Catalog(**{**cat.__dict__, "event_pix_off": np.concatenate([[0], epo])})
+    # an extra last event with two empty pixels
+    pso = np.asarray(cat.pix_samp_off, np.int64)
+    empty_pix = synth.Catalog(**{**cat.__dict__, "event_pix_off": np.concatenate([epo, [epo[-1] + 2]]),
+                                 "pix_samp_off": np.concatenate([pso, [pso[-1], pso[-1]]]),
+                                 "pix_los_row": np.concatenate([cat.pix_los_row, [0, 0]]).astype(np.int32)})
+    for c, i_empty, others in ((no_pix, 0, slice(1, None)), (empty_pix, cat.n_events, slice(0, -1))):
+        for fn, r0 in ((O.loglike, ref), (O.loglike_kde, ref_kde)):
+            r = fn(c, lam)
+            assert r["flags"] == O.FLAG_EVENT_NO_PIXEL and r["logL"] == -math.inf
+            assert r["logL_event"][i_empty] == -math.inf and r["neff_event"][i_empty] == 0.0
+            np.testing.assert_array_equal(r["logL_event"][others], r0["logL_event"])
+
+
 def test_table_ii_fixture():
     with open(os.path.join(HERE, "golden", "table_ii.json")) as f:
         g = json.load(f)
