@@ -265,3 +265,54 @@ def test_event_merge_paths(mods, precision):
                 assert rel_close(float(r["logL"][b]), ref["logL"], tol)
                 check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
         lik.close()
+
+
+def test_degenerate_catalogues(mods):
+    """An event with no pixels and an event whose pixels hold no samples (L_i = 0:
+    flag 2, ln L = -inf), and injections all beyond z_max (alpha = 0: flag 4),
+    with and without the gradient, against the oracle."""
+    import dataclasses
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    lam = synth.draw_lambdas(3, seed=67)
+    lam[0] = synth.fiducial_lambda()
+    base = ragged_catalog(synth, [[64, 65], [], [0, 0], [7]])
+    far = dataclasses.replace(base, inj_dl=np.full_like(base.inj_dl, 1e6))
+    for name, cat in (("empty events", base), ("alpha = 0", far)):
+        log(f"  [{name}]")
+        lik = mods["binding"].DarkSirenLikelihood(cat)
+        lt = torch.tensor(lam, device="cuda")
+        for grad in (False, True):
+            r = lik.loglike_grad(lt, per_event=True) if grad else lik.loglike(lt, per_event=True)
+            torch.cuda.synchronize()
+            for b in range(len(lam)):
+                ref = O.loglike(cat, lam[b], margins=True)
+                assert int(r["flags"][b]) == ref["flags"] != 0, (name, b, int(r["flags"][b]), ref["flags"])
+                assert float(r["logL"][b]) == -math.inf
+                ev = r["logL_event"][b].cpu().numpy()
+                assert np.array_equal(np.isneginf(ev), np.isneginf(ref["logL_event"]))
+                check_events(ev, r["neff_event"][b].cpu().numpy(), ref, TOL_LOGL_FP32)
+                if grad:
+                    assert not r["grad"][b].any()
+        lik.close()
+
+
+def test_maximum_batch(mods):
+    """B = max_batch (4096 points) with the gradient on a small catalogue:
+    sampled points against the oracle, both ends of the batch included."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=3, n_inj=3000)
+    B = 4096
+    lam = synth.draw_lambdas(B, seed=71)
+    lam[0] = synth.fiducial_lambda()
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    assert int(lik.info("max_batch")) == B
+    r = lik.loglike_grad(torch.tensor(lam, device="cuda"))
+    torch.cuda.synchronize()
+    log(f"  tile {int(lik.info('lambda_tile_used'))}, {int(np.isfinite(r['logL'].cpu().numpy()).sum())} finite")
+    for b in (0, 1, 63, 64, 2047, 4094, 4095):
+        ref = O.loglike(cat, lam[b], grad=True)
+        assert int(r["flags"][b]) == ref["flags"], b
+        if not ref["flags"]:
+            assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32), b
+            check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
+    lik.close()
