@@ -29,7 +29,7 @@ hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int gri
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
 hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st);
-hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64_t n_pix, int n_events, int B,
+hipError_t launch_kde_events(const double* pix, const int64_t* ev_part_off, int64_t n_parts, int n_events, int B,
                              double* ev, hipStream_t st);
 hipError_t init_kernel_attrs();
 hipError_t init_kde_attrs();
@@ -109,7 +109,10 @@ struct dsl_handle {
   double z_max = 0;
   std::vector<int64_t> epo, pso;   // host copies (work-list builder)
   DevBuf samp, inj, pix_off, pix_row, los, sky, ln_ns;
-  DevBuf ev_pix_off, perm;         // KDE numerator: event -> pixels, per-pixel d_L order
+  // KDE numerator: pixel parts and event -> parts (split grid stage), event ->
+  // pixels, per-pixel d_L order
+  DevBuf kde_parts, ev_part_off, ev_pix_off, perm;
+  int64_t n_kde_parts = 0, built_part_size = 0, max_pix_samples = 0;
   // work list (for the current chunk size)
   int64_t built_chunk = -1;
   DevBuf items, order, ev_item_off, splits;
@@ -423,6 +426,47 @@ int combine_slices(const dsl_handle* h, int B) {
   return std::max(1, std::min(32, std::min(by_items, by_cu)));
 }
 
+// Part size of the KDE grid stage for batches of B points: a pixel holding more
+// than half the samples a wavefront handles on average over the launch would be
+// a long tail, so pixels above max(KDE_PART, that half) are split into parts of
+// that many samples (a multiple of 16).  0: no pixel is split.
+int64_t kde_part_size(const dsl_handle* h, int B) {
+  const double per_wave = (double)h->n_samp * B / (4.0 * 16 * h->n_cu);
+  int64_t P = std::max<int64_t>(KDE_PART, (int64_t)std::ceil(0.5 * per_wave));
+  P = (P + 15) / 16 * 16;
+  return h->max_pix_samples > P ? P : 0;
+}
+
+// The part list for part size P (rebuilt when P changes; graphs read it at
+// replay, and a reallocation drops them through the workspace signature).
+int build_kde_parts(dsl_handle* h, int64_t P) {
+  if (P == 0 || P == h->built_part_size) return DSL_OK;
+  std::vector<KdePart> parts;
+  std::vector<int64_t> ev_part(h->n_events + 1);
+  for (int64_t e = 0; e < h->n_events; ++e) {
+    ev_part[e] = (int64_t)parts.size();
+    for (int64_t j = h->epo[e]; j < h->epo[e + 1]; ++j) {
+      const int64_t n = h->pso[j + 1] - h->pso[j];
+      int64_t lo = 0;
+      do {
+        KdePart pt;
+        pt.pix = j;
+        pt.lo = (int32_t)lo;
+        pt.hi = (int32_t)std::min<int64_t>(n, lo + P);
+        parts.push_back(pt);
+        lo += P;
+      } while (lo < n);
+    }
+  }
+  ev_part[h->n_events] = (int64_t)parts.size();
+  int rc;
+  if ((rc = upload(h->kde_parts, parts.data(), sizeof(KdePart) * parts.size()))) return rc;
+  if ((rc = upload(h->ev_part_off, ev_part.data(), sizeof(int64_t) * ev_part.size()))) return rc;
+  h->n_kde_parts = (int64_t)parts.size();
+  h->built_part_size = P;
+  return DSL_OK;
+}
+
 // Events spanning many work items (the monte-carlo numerator) are merged by one
 // wavefront each before the combine, instead of one thread walking the items.
 bool merge_events(const dsl_handle* h) {
@@ -445,7 +489,8 @@ int ensure_workspace(dsl_handle* h, int B, bool grad) {
   if ((e = h->part.ensure(sizeof(double) * nf * (size_t)B * std::max(h->n_items, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (partials)");
   if (h->numerator == 1 &&
-      (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_pix, 1))) != hipSuccess)
+      (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B *
+                              std::max<int64_t>(kde_part_size(h, B) ? h->n_kde_parts : h->n_pix, 1))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
   if ((e = h->cpart.ensure(sizeof(double) * NF_CSLICE * (size_t)B * combine_slices(h, B))) != hipSuccess)
     return fail(DSL_ENOMEM, "workspace (combine slices)");
@@ -523,6 +568,9 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
     k.n_z = h->n_z;
     k.z_max = h->z_max;
     k.n_pix = h->n_pix;
+    const bool split = kde_part_size(h, B) != 0;   // part list built for this B before the launch
+    k.parts = split ? h->kde_parts.as<KdePart>() : nullptr;
+    k.n_parts = split ? h->n_kde_parts : h->n_pix;
     k.lamc = h->lamc.p;
     k.cos_tab = h->cos_tab.p;
     k.win_tab = h->win_tab.p;
@@ -535,7 +583,8 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
     k.out = h->kde_out.as<double>();
     k.evals = h->kde_evals.as<unsigned long long>();
     HIPCHK(launch_kde(h->fp32, k, h->n_cu, st));
-    HIPCHK(launch_kde_events(h->kde_out.as<double>(), h->ev_pix_off.as<int64_t>(), h->n_pix, (int)h->n_events, B,
+    HIPCHK(launch_kde_events(h->kde_out.as<double>(), split ? h->ev_part_off.as<int64_t>() : h->ev_pix_off.as<int64_t>(),
+                             k.n_parts, (int)h->n_events, B,
                              h->kde_ev.as<double>(), st));
   } else {
     HIPCHK(launch_gate_split(gs, st));
@@ -586,12 +635,13 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   h->last_gl = cfg.GL;
   int rc;
   if ((rc = build_items(h, cfg.chunk))) return rc;
+  if (h->numerator == 1 && (rc = build_kde_parts(h, kde_part_size(h, B)))) return rc;
   if ((rc = ensure_workspace(h, B, grad))) return rc;
   // captured graphs hold workspace addresses: drop them all when any buffer moved
   const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
                                         h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
-                                        h->ev_rec.p};
+                                        h->ev_rec.p,  h->kde_parts.p, h->ev_part_off.p};
   if (sig != h->ws_sig) {
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
@@ -768,6 +818,7 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   if ((rc = upload(h->los, d->los, sizeof(float) * d->n_los_rows * (size_t)d->n_z))) return rc;
   if ((rc = upload(h->sky, d->sky_z, sizeof(float) * d->n_z))) return rc;
   if ((rc = upload(h->ln_ns, ln_ns.data(), sizeof(double) * ln_ns.size()))) return rc;
+  for (int64_t j = 0; j < d->n_pix; ++j) h->max_pix_samples = std::max(h->max_pix_samples, h->pso[j + 1] - h->pso[j]);
   if ((rc = upload(h->ev_pix_off, d->event_pix_off, sizeof(int64_t) * (d->n_events + 1)))) return rc;
   {
     // per pixel, local sample indices in ascending d_L (ties by position): the
@@ -889,7 +940,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   }
   else if (k == "device_bytes") {
     *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
-                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_pix_off.n +
+                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_part_off.n + h->kde_parts.n + h->ev_pix_off.n +
                   h->kde_out.n + h->kde_ev.n + h->ev_rec.n + h->cpart.n);
   } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
   return DSL_OK;

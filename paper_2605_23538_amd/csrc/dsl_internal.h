@@ -122,6 +122,16 @@ struct SweepArgs {
 constexpr int NF_KDE = 4;
 // Largest redshift grid of the KDE numerator.
 constexpr int KDE_GRID_MAX = 1024;
+// Pixels with more samples than this are split into parts of this many
+// samples for the KDE's grid stage (one wavefront task per part).
+constexpr int KDE_PART = 256;
+
+// One part of a pixel for the KDE numerator: samples [lo, hi) of the pixel
+// (local indices) in the grid stage; part 0 of a pixel has lo = 0.
+struct KdePart {
+  int64_t pix;
+  int32_t lo, hi;
+};
 
 struct KdeArgs {
   const void* samp;          // Samp<T>[n_samp]
@@ -132,6 +142,8 @@ struct KdeArgs {
   int32_t n_z;
   double z_max;
   int64_t n_pix;
+  const KdePart* parts;      // [n_parts], pixel-major; null: one part per pixel (n_parts = n_pix)
+  int64_t n_parts;
   const void* lamc;          // LamC<T>[B]
   const void* cos_tab;       // [B][NU+1] of T2
   const void* win_tab;       // [B][NW+1] of T2
@@ -141,7 +153,7 @@ struct KdeArgs {
   double tau;                // grid margin in bandwidths
   double neff_min;
   int32_t gate_mode;
-  double* out;               // [B][n_pix][NF_KDE]
+  double* out;               // [B][n_parts][NF_KDE]: {R, T, S1, S2}; S1, S2 only on part 0
   unsigned long long* evals; // [0] (sample, node) kernel terms, [1] grid nodes of the launch (zeroed before it)
 };
 

@@ -112,7 +112,9 @@ template <> struct KdeWaves<double> { static constexpr int W = 2; };
 // ROWPIX (batches of fewer than four points): the four rows of a wavefront take
 // four consecutive (pixel, point) pairs, pixel-major, instead of four points of
 // one pixel, so no row idles; pixel bounds and loop counts are then per row.
-template <typename T, int LT, bool ROWPIX>
+// SPLIT: tasks are pixel parts (a.parts) whose grid stage covers samples
+// [lo, hi) of the pixel; otherwise one part per pixel.
+template <typename T, int LT, bool ROWPIX, bool SPLIT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>::W))) void kde_kernel(KdeArgs a) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW;
@@ -145,28 +147,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
   const TabView<T> tv{cosL, winL, nullptr};
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
   const int ng = (nl + 3) >> 2;   // groups of four points in this tile
-  const int64_t n_pairs = a.n_pix * nl;
-  const int64_t n_tasks = ROWPIX ? (n_pairs + 3) / 4 : a.n_pix * ng;
+  const int64_t n_units = SPLIT ? a.n_parts : a.n_pix;   // pixel parts, or whole pixels
+  const int64_t n_pairs = n_units * nl;
+  const int64_t n_tasks = ROWPIX ? (n_pairs + 3) / 4 : n_units * ng;
   for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < n_tasks; t += (int64_t)gridDim.x * nwaves) {
-    int64_t p;
-    int l;   // this row's pixel and point in the tile
+    int64_t pi;
+    int l;   // this row's pixel part and point in the tile
     bool act;
     if constexpr (ROWPIX) {
       const int64_t i = 4 * t + q;
       act = i < n_pairs;
-      p = act ? i / nl : 0;
-      l = act ? (int)(i - p * nl) : 0;
+      pi = act ? i / nl : 0;
+      l = act ? (int)(i - pi * nl) : 0;
     } else {
-      p = t / ng;
-      l = 4 * (int)(t - p * ng) + q;
+      pi = t / ng;
+      l = 4 * (int)(t - pi * ng) + q;
       act = l < nl;
     }
+    KdePart part{pi, 0, 0};
+    if constexpr (SPLIT) part = a.parts[pi];
+    const int64_t p = part.pix;
     const int b = tile * LT + (act ? l : 0);
     const LamC<T> c = lamc[b];
     const bool live = act && c.valid;
-    double* out = a.out + ((size_t)b * a.n_pix + p) * NF_KDE;
+    double* out = a.out + ((size_t)b * n_units + pi) * NF_KDE;
     const int64_t s0 = a.pix_off[p];
+    // pass A and the bandwidth take the whole pixel, the grid stage [lo, hi)
     const int n = ROWPIX && !act ? 0 : (int)(a.pix_off[p + 1] - s0);
+    const int lo = SPLIT && !(ROWPIX && !act) ? part.lo : 0;
+    const int hi = SPLIT && !(ROWPIX && !act) ? (part.hi < n ? part.hi : n) : n;
     // ---- pass A
     PixAcc<false, T> pa;
     pa.zero();
@@ -210,7 +219,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
       return (double)z_of_u<T, LT>(sp.dlc * c.H0, c, tv, l);
     };
-    auto z_w = [&](int c0, T& z, T& w) {   // the lane's redshift and scaled weight in chunk c0
+    // the lane's redshift and scaled weight in the chunk from c0 (samples below lim)
+    auto z_w = [&](int c0, int lim, T& z, T& w) {
       if (n <= 16) {
         z = z1;
         w = (z1 >= (T)0 && lin1 > (T)0) ? ldexp(lin1, ne1 - R) : (T)0;
@@ -219,7 +229,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const int k = c0 + kl;
       z = (T)-1;
       w = (T)0;
-      if (k < n && live) {
+      if (k < lim && live) {
         int ne;
         T lin;
         eval_weight<T, LT, false, true>(samp[s0 + k], c, tv, l, nullptr, 0, (T)0, ne, lin, nullptr, &z);
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
           double num = 0.0, den = 0.0;
           for (int c0 = 0; c0 < n; c0 += 16) {
             T z, w;
-            z_w(c0, z, w);
+            z_w(c0, n, z, w);
             if (z >= (T)0) {
               const double d = (double)z - Q, u = d * iu, uu = u * u;
               if (fabs(u) < 1.0) {
@@ -288,10 +298,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
     const bool kde_row = pass && h > 0.0 && isfinite(h);
     double Tt = 0.0;
     if (pass && !kde_row) {
-      // zero bandwidth: point masses at the samples
-      for (int c0 = 0; c0 < n; c0 += 16) {
+      // zero bandwidth: point masses at the part's samples
+      for (int c0 = lo; c0 < hi; c0 += 16) {
         T z, w;
-        z_w(c0, z, w);
+        z_w(c0, hi, z, w);
         if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(c, z));
       }
       Tt = row_reduce(Tt, [](double x, double y) { return x + y; });
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const T ra = -(c.gm3 + (T)2), rb = c.gk - (c.gm3 + (T)2), rc = -c.gk * c.Lp;
       const unsigned nz2 = (unsigned)(a.n_z - 2);
       const double dz16 = 16.0 * dz;
-      if (kl == 0 && a.evals) atomicAdd(&work[1], (unsigned long long)a.n_grid);
+      if (kl == 0 && a.evals && lo == 0) atomicAdd(&work[1], (unsigned long long)a.n_grid);
       for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
         T zgs[NB], vg[NB];
         // Node g = g0 + kl + 16 i.  Trapezoid weight min(max(n_grid - 1/2 - g, 0), 1):
@@ -330,11 +340,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
           zgs[i] = zg * invh;
         }
         if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
-        for (int c0 = 0; c0 < n; c0 += 16) {
+        for (int c0 = lo; c0 < hi; c0 += 16) {
           T z, w;
-          z_w(c0, z, w);
+          z_w(c0, hi, z, w);
           const T zsc = z * invh;
-          const int cnt = n - c0 < 16 ? n - c0 : 16;
+          const int cnt = hi - c0 < 16 ? hi - c0 : 16;
           if (g0 == 0) {
             const unsigned long long m = __ballot(w > (T)0);
             if (kl == 0 && a.evals)
@@ -366,8 +376,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
     if (act && kl == 0) {
       out[0] = pass ? (double)R : 0.0;
       out[1] = pass ? Tt : 0.0;
-      out[2] = pass ? S1 : 0.0;
-      out[3] = pass ? S2 : 0.0;
+      out[2] = pass && lo == 0 ? S1 : 0.0;
+      out[3] = pass && lo == 0 ? S2 : 0.0;
     }
   }
   __syncthreads();
@@ -378,20 +388,21 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
-// Per (event, point): merge the event's pixel records {R, T, S1, S2} (pixels
-// with S1 > 0, i.e. passing the gate) under one exponent.  One wavefront per
-// pair; lanes stride over the pixels, then a symmetric butterfly.
-__global__ __launch_bounds__(256) void kde_event_kernel(const double* __restrict__ pix, const int64_t* ev_pix_off,
-                                                        int64_t n_pix, int n_events, int B, double* __restrict__ ev) {
+// Per (event, point): merge the event's pixel-part records {R, T, S1, S2} of
+// passing pixels (S1 > 0 on a pixel's first part, T > 0 on its others) under
+// one exponent.  One wavefront per pair; lanes stride over the parts, then a
+// symmetric butterfly.
+__global__ __launch_bounds__(256) void kde_event_kernel(const double* __restrict__ pix, const int64_t* ev_part_off,
+                                                        int64_t n_parts, int n_events, int B, double* __restrict__ ev) {
   const int lane = threadIdx.x & 63;
   const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (w >= (int64_t)n_events * B) return;
   const int b = (int)(w / n_events), e = (int)(w % n_events);
   int R = R_SENTINEL;
   double T = 0, S1 = 0, S2 = 0;
-  for (int64_t p = ev_pix_off[e] + lane; p < ev_pix_off[e + 1]; p += 64) {
-    const double* r = pix + ((size_t)b * n_pix + p) * NF_KDE;
-    if (!(r[2] > 0)) continue;
+  for (int64_t p = ev_part_off[e] + lane; p < ev_part_off[e + 1]; p += 64) {
+    const double* r = pix + ((size_t)b * n_parts + p) * NF_KDE;
+    if (!(r[2] > 0) && !(r[1] > 0)) continue;
     const int Rp = (int)r[0];
     if (R == R_SENTINEL) R = Rp;
     else if (Rp > R) {
@@ -433,9 +444,9 @@ static size_t kde_lds_bytes() {
   return sizeof(T2) * (size_t)KdeTile<T>::LT * ((Tab<T>::NU + 1) + (Tab<T>::NW + 1));
 }
 
-template <typename T, bool ROWPIX>
+template <typename T, bool ROWPIX, bool SPLIT>
 static hipError_t kde_attr() {
-  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, ROWPIX>,
+  return hipFuncSetAttribute((const void*)kde_kernel<T, KdeTile<T>::LT, ROWPIX, SPLIT>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kde_lds_bytes<T>());
 }
 
@@ -443,14 +454,21 @@ template <typename T>
 static hipError_t kde_t(const KdeArgs& a, int n_cu, hipStream_t st) {
   constexpr int LT = KdeTile<T>::LT;
   const int n_tiles = (a.B + LT - 1) / LT;
-  const bool rowpix = a.B < 4;   // fewer points than rows: rows take pixels
-  const int64_t tasks = rowpix ? (a.n_pix * a.B + 3) / 4 : a.n_pix * (((a.B < LT ? a.B : LT) + 3) / 4);
+  const bool rowpix = a.B < 4;   // fewer points than rows: rows take pixel parts
+  const int64_t tasks = rowpix ? (a.n_parts * a.B + 3) / 4 : a.n_parts * (((a.B < LT ? a.B : LT) + 3) / 4);
   int grid_x = (2 * n_cu + n_tiles - 1) / n_tiles;
   if ((int64_t)grid_x * 8 > tasks) grid_x = (int)((tasks + 7) / 8);
   if (grid_x < 1) grid_x = 1;
   if (a.n_grid < 2 || a.n_grid > KDE_GRID_MAX) return hipErrorInvalidValue;
-  if (rowpix) kde_kernel<T, LT, true><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
-  else kde_kernel<T, LT, false><<<dim3(grid_x, n_tiles), 512, kde_lds_bytes<T>(), st>>>(a);
+  const dim3 grid(grid_x, n_tiles);
+  const size_t lds = kde_lds_bytes<T>();
+  if (a.parts) {
+    if (rowpix) kde_kernel<T, LT, true, true><<<grid, 512, lds, st>>>(a);
+    else kde_kernel<T, LT, false, true><<<grid, 512, lds, st>>>(a);
+  } else {
+    if (rowpix) kde_kernel<T, LT, true, false><<<grid, 512, lds, st>>>(a);
+    else kde_kernel<T, LT, false, false><<<grid, 512, lds, st>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -460,24 +478,28 @@ hipError_t launch_kde(int fp32, const KdeArgs& a, int n_cu, hipStream_t st) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (a.n_pix == 0) return hipSuccess;
+  if (a.n_parts == 0) return hipSuccess;
   return fp32 ? kde_t<float>(a, n_cu, st) : kde_t<double>(a, n_cu, st);
 }
 
-hipError_t launch_kde_events(const double* pix, const int64_t* ev_pix_off, int64_t n_pix, int n_events, int B,
+hipError_t launch_kde_events(const double* pix, const int64_t* ev_part_off, int64_t n_parts, int n_events, int B,
                              double* ev, hipStream_t st) {
   const int64_t threads = (int64_t)n_events * B * 64;
-  kde_event_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(pix, ev_pix_off, n_pix, n_events, B, ev);
+  kde_event_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(pix, ev_part_off, n_parts, n_events, B, ev);
   return hipGetLastError();
 }
 
 // Raise the dynamic-LDS limit of every KDE variant (once, outside any capture).
 hipError_t init_kde_attrs() {
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = kde_attr<float, false>();
-  if (e == hipSuccess) e = kde_attr<float, true>();
-  if (e == hipSuccess) e = kde_attr<double, false>();
-  if (e == hipSuccess) e = kde_attr<double, true>();
+  if (e == hipSuccess) e = kde_attr<float, false, false>();
+  if (e == hipSuccess) e = kde_attr<float, true, false>();
+  if (e == hipSuccess) e = kde_attr<float, false, true>();
+  if (e == hipSuccess) e = kde_attr<float, true, true>();
+  if (e == hipSuccess) e = kde_attr<double, false, false>();
+  if (e == hipSuccess) e = kde_attr<double, true, false>();
+  if (e == hipSuccess) e = kde_attr<double, false, true>();
+  if (e == hipSuccess) e = kde_attr<double, true, true>();
   return e;
 }
 

@@ -112,6 +112,39 @@ def test_fewer_points_than_rows(env, precision, B, bandwidth):
         _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("B", [1, 5])
+@pytest.mark.parametrize("bandwidth", ["silverman", "biweight"])
+def test_split_pixels(env, precision, B, bandwidth):
+    """Pixels above 256 samples are split for the grid stage (each part keeps
+    the whole pixel's gate and bandwidth): sizes at and around the part size."""
+    synth = env["synth"]
+    log(f"[kde split pixels B={B} {precision} {bandwidth}]")
+    cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
+    lam = synth.draw_lambdas(B, seed=73)
+    lam[0] = synth.fiducial_lambda()
+    tol = TOL_LOGL_FP32 if precision == "fp32" else TOL_LOGL_FP64
+    for gate in (0, 2):
+        r = _run(env, cat, lam, precision, kde_bandwidth=bandwidth, gate_mode=gate)
+        _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
+
+
+def test_large_pixels_unsplit(env):
+    """With many points per launch large pixels stay whole (each wavefront has
+    many tasks, so none is a long tail): 4096 points, sampled against the oracle."""
+    torch, O, synth = env["torch"], env["O"], env["synth"]
+    log("[kde large pixels, 4096 points]")
+    cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
+    lam = synth.draw_lambdas(4096, seed=79)
+    lam[0] = synth.fiducial_lambda()
+    r = _run(env, cat, lam)
+    for b in (0, 1, 2048, 4095):
+        ref = O.loglike_kde(cat, lam[b], margins=True)
+        assert int(r["flags"][b]) == ref["flags"], b
+        if not ref["flags"]:
+            assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32), (b, float(r["logL"][b]), ref["logL"])
+
+
 @pytest.mark.parametrize("n_grid", [2, 64, 300, 1024])
 def test_grid_sizes(env, n_grid):
     """Grids below, at and above one node per lane, up to 16 nodes per lane."""
