@@ -24,7 +24,7 @@ size_t sweep_lds_bytes(int fp32, int GL, bool grad);
 hipError_t launch_pack(int fp32, const double* m1, const double* m2, const double* dl, const double* lnp,
                        int64_t n, void* out, hipStream_t st);
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st);
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, int threads, hipStream_t st);
 hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
@@ -517,9 +517,11 @@ struct CallOut {
 int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& o, const SweepCfg& cfg,
             hipStream_t st, bool timed) {
   if (timed) HIPCHK(hipEventRecord(h->ev[0], st));
+  // setup: two workgroups per point; wide ones shorten a call when they leave CUs free
+  const int setup_threads = 2 * B < h->n_cu ? 1024 : 256;
   HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, h->lamc.p, h->cos_tab.p, h->win_tab.p,
                       grad ? h->wg_tab.p : nullptr, h->valid.as<int>(), grad ? h->gmap.as<double>() : nullptr,
-                      st));
+                      setup_threads, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
   SweepArgs a;
   a.samp = h->samp.p;

@@ -1003,14 +1003,16 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
   return hipGetLastError();
 }
 
+// threads: per workgroup, 256 ... SETUP_THREADS (the loops stride by the block size).
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, hipStream_t st) {
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, int threads, hipStream_t st) {
+  if (threads < 256 || threads > SETUP_THREADS || threads % 64) return hipErrorInvalidValue;
   if (fp32)
-    setup_kernel<float><<<dim3(B, 2), SETUP_THREADS, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
-                                            (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
+    setup_kernel<float><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
+                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
   else
-    setup_kernel<double><<<dim3(B, 2), SETUP_THREADS, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
-                                             (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
+    setup_kernel<double><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
+                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
   return hipGetLastError();
 }
 
