@@ -399,6 +399,11 @@ void block_shape(const dsl_handle* h, bool grad, int GL, int shape, SweepCfg& c)
   if (h->fp32 && grad && shape == 0) {
     c.waves = GL == 64 ? 12 : 4;
     c.wg_per_cu = GL == 64 ? 1 : 3;
+  } else if (h->fp32 && !grad && shape == 2) {
+    // the FP32 forward sweep of one point fits 6 waves per SIMD (<= 84 VGPRs):
+    // three 8-wavefront workgroups per CU hide more of the table-gather latency
+    c.waves = 8;
+    c.wg_per_cu = 3;
   } else {
     c.waves = 8;
     c.wg_per_cu = 2;
@@ -414,7 +419,7 @@ SweepCfg config_for(dsl_handle* h, int B, bool grad) {
   if (!h->fp32 && c.GL > 4) c.GL = 4;
   if (h->chunk_opt) c.chunk = h->chunk_opt;
   if (c.chunk <= 0) c.chunk = auto_chunk(h, c.GL);
-  if (it == h->tuned.end() || h->lambda_tile) block_shape(h, grad, c.GL, 0, c);
+  if (it == h->tuned.end() || h->lambda_tile) block_shape(h, grad, c.GL, h->fp32 && !grad && c.GL == 1 ? 2 : 0, c);
   return c;
 }
 
@@ -659,7 +664,7 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   k.grad = grad;
   k.st = st;
   const void* ptrs[8] = {d_lambda, o.logL, o.grad, o.logL_event, o.neff_event, o.neff_sel, o.flags,
-                         (const void*)(intptr_t)((cfg.GL * 1000003 + cfg.chunk) * 64 + cfg.waves)};
+                         (const void*)(intptr_t)(((cfg.GL * 1000003 + cfg.chunk) * 64 + cfg.waves) * 8 + cfg.wg_per_cu)};
   std::memcpy(k.ptrs, ptrs, sizeof(ptrs));
   auto it = h->graphs.find(k);
   if (it == h->graphs.end()) {
@@ -700,8 +705,12 @@ std::vector<SweepCfg> tune_candidates(const dsl_handle* h, int B, bool grad) {
       ch = std::max<int64_t>(64, std::min<int64_t>(65536, ch));
       if (std::find(chunks.begin(), chunks.end(), ch) == chunks.end()) chunks.push_back(ch);
     }
-    const int shapes = h->fp32 && grad ? 2 : 1;
-    for (int shape = 0; shape < shapes; ++shape)
+    // workgroup shapes: both FP32-adjoint shapes; for forward one-point tiles
+    // also three workgroups per CU
+    std::vector<int> shapes{0};
+    if (h->fp32 && grad) shapes.push_back(1);
+    if (h->fp32 && !grad && gl == 1) shapes.push_back(2);
+    for (int shape : shapes)
       for (int64_t ch : chunks) {
         SweepCfg c;
         c.GL = gl;
@@ -718,7 +727,7 @@ std::vector<SweepCfg> tune_candidates(const dsl_handle* h, int B, bool grad) {
 bool cached_cfg_ok(const dsl_handle* h, bool grad, const SweepCfg& c) {
   if (c.chunk < 64 || c.chunk > 65536) return false;
   if (!(c.GL == 1 || c.GL == 4 || (h->fp32 && (c.GL == 16 || c.GL == 64)))) return false;
-  for (int shape = 0; shape < 2; ++shape) {
+  for (int shape = 0; shape < 3; ++shape) {
     SweepCfg s;
     block_shape(h, grad, c.GL, shape, s);
     if (s.waves == c.waves && s.wg_per_cu == c.wg_per_cu) return true;
