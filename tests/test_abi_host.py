@@ -66,6 +66,7 @@ def _desc(binding, **over):
     (dict(dl=np.array([30.0, -1.0, 40.0])), "finite"),
     (dict(los=np.array([1, 1, 1, -1, 1, 1, 1, 1], np.float32)), "LOS"),
     (dict(ilp=np.array([0.0, float("inf"), 0.0])), "inj_ln_pdraw"),
+    (dict(epo=np.array([0, 1], np.int64)), "event_pix_off"),
 ])
 def test_create_rejects_malformed_catalogue(over, msg):
     binding, lib = _lib()
@@ -84,3 +85,44 @@ def test_null_arguments():
     assert lib.dsl_loglike(None, None, 1, None, None, None, None, None, None) == 4
     assert lib.dsl_get_timing(None, None, None, None) == 4
     lib.dsl_destroy(None)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_events", 0, "n_events"),
+    ("n_inj", 0, "injection"),
+    ("n_draw", 2, "n_draw"),
+    ("n_z", 1, "n_z"),
+    ("precision", 7, "precision"),
+    ("max_samples_per_pixel", -1, "max_samples_per_pixel"),
+])
+def test_create_rejects_bad_sizes(field, value, msg):
+    """Descriptor sizes out of range are rejected before anything is uploaded."""
+    binding, lib = _lib()
+    d, keep = _desc(binding)
+    setattr(d, field, value)
+    h = C.c_void_p()
+    assert lib.dsl_create(C.byref(d), C.byref(h)) == 1 and not h.value
+    assert msg in lib.dsl_last_error().decode()
+
+
+def test_binding_requires_a_gpu():
+    """No fallback: without a GPU the binding refuses to build a likelihood."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2605_23538_amd import binding, synth
+    cat = synth.make_catalog("c1", n_events=2, n_inj=100)
+    with pytest.raises(binding.DSLError, match="GPU"):
+        binding.DarkSirenLikelihood(cat)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus 2 exits with a message before any GPU work."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
