@@ -166,7 +166,8 @@ int dsl_set_option(dsl_handle* h, const char* key, double value);
  * of the last call), "device_bytes" (device memory the handle holds),
  * "kde_evals" and "kde_nodes" (of the last call with the KDE numerator: the
  * (sample, grid node) kernel terms and the grid nodes evaluated; both wait for
- * the device), or, after a call made with option
+ * the device), "kde_units" (the grid-stage units of that call: n_pix, or more
+ * when large pixels were split into parts), or, after a call made with option
  * "timing" = 1, "ms_sweep_only" (the weight sweep alone) and "ms_pixels" (the
  * per-pixel stage after it: the KDE kernel, or the gate of split pixels).
  * Returns DSL_EINVAL for unknown keys. */

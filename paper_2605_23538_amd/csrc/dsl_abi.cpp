@@ -113,6 +113,7 @@ struct dsl_handle {
   // pixels, per-pixel d_L order
   DevBuf kde_parts, ev_part_off, ev_pix_off, perm;
   int64_t n_kde_parts = 0, built_part_size = 0, max_pix_samples = 0;
+  int64_t last_kde_units = 0;   // grid-stage units of the last KDE call (pixels or pixel parts)
   // work list (for the current chunk size)
   int64_t built_chunk = -1;
   DevBuf items, order, ev_item_off, splits;
@@ -578,6 +579,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
     const bool split = kde_part_size(h, B) != 0;   // part list built for this B before the launch
     k.parts = split ? h->kde_parts.as<KdePart>() : nullptr;
     k.n_parts = split ? h->n_kde_parts : h->n_pix;
+    h->last_kde_units = k.n_parts;
     k.lamc = h->lamc.p;
     k.cos_tab = h->cos_tab.p;
     k.win_tab = h->win_tab.p;
@@ -930,6 +932,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
   else if (k == "chunk") *v = (double)(h->chunk_opt ? h->chunk_opt : h->built_chunk);
   else if (k == "n_cu") *v = h->n_cu;
   else if (k == "lambda_tile_used") *v = h->last_gl;
+  else if (k == "kde_units") *v = (double)h->last_kde_units;
   else if (k == "kde_evals" || k == "kde_nodes") {
     // of the last KDE call (waits for the device): (sample, grid node) kernel
     // terms, and grid nodes (each a prior and rate evaluation) over all

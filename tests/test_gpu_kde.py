@@ -118,31 +118,42 @@ def test_fewer_points_than_rows(env, precision, B, bandwidth):
 def test_split_pixels(env, precision, B, bandwidth):
     """Pixels above 256 samples are split for the grid stage (each part keeps
     the whole pixel's gate and bandwidth): sizes at and around the part size."""
-    synth = env["synth"]
+    torch, synth = env["torch"], env["synth"]
     log(f"[kde split pixels B={B} {precision} {bandwidth}]")
     cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
     lam = synth.draw_lambdas(B, seed=73)
     lam[0] = synth.fiducial_lambda()
     tol = TOL_LOGL_FP32 if precision == "fp32" else TOL_LOGL_FP64
     for gate in (0, 2):
-        r = _run(env, cat, lam, precision, kde_bandwidth=bandwidth, gate_mode=gate)
+        lik = env["binding"].DarkSirenLikelihood(cat, precision=precision, numerator="kde",
+                                                 kde_bandwidth=bandwidth, gate_mode=gate)
+        r = lik.loglike(torch.tensor(lam, device="cuda"), per_event=True)
+        torch.cuda.synchronize()
+        # parts of 256: 1 + 2, 2 + 1 + 3, 4
+        assert lik.info("kde_units") == 13
+        lik.close()
         _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
 
 
 def test_large_pixels_unsplit(env):
-    """With many points per launch large pixels stay whole (each wavefront has
-    many tasks, so none is a long tail): 4096 points, sampled against the oracle."""
-    torch, O, synth = env["torch"], env["O"], env["synth"]
-    log("[kde large pixels, 4096 points]")
-    cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
+    """With enough work per wavefront large pixels stay whole: 4096 points on a
+    catalogue whose average work per wavefront exceeds twice its largest pixel
+    (1000 samples), sampled against the oracle."""
+    torch, O, synth, binding = env["torch"], env["O"], env["synth"], env["binding"]
+    log("[kde large pixels, 4096 points, unsplit]")
+    cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]] + [[500, 500]] * 20, n_inj=500)
     lam = synth.draw_lambdas(4096, seed=79)
     lam[0] = synth.fiducial_lambda()
-    r = _run(env, cat, lam)
+    lik = binding.DarkSirenLikelihood(cat, numerator="kde")
+    r = lik.loglike(torch.tensor(lam, device="cuda"))
+    torch.cuda.synchronize()
+    assert lik.info("kde_units") == len(cat.pix_samp_off) - 1   # no pixel split
     for b in (0, 1, 2048, 4095):
         ref = O.loglike_kde(cat, lam[b], margins=True)
         assert int(r["flags"][b]) == ref["flags"], b
         if not ref["flags"]:
             assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32), (b, float(r["logL"][b]), ref["logL"])
+    lik.close()
 
 
 @pytest.mark.parametrize("n_grid", [2, 64, 300, 1024])
@@ -239,4 +250,26 @@ def test_kde_work_counters(env):
     assert n_h > 0 and lik.info("kde_nodes") == n_h * B * n_grid
     ev = lik.info("kde_evals")
     assert ev % n_grid == 0 and 0 < ev <= cat.n_samp * B * n_grid
+    lik.close()
+
+
+def test_part_list_rebuilds_with_graphs(env):
+    """One handle, graph replay on, batches that need different part sizes
+    (256 samples for one point, 320 for 4096 points): every call equals an
+    eager call of the same batch, bitwise."""
+    torch, synth, binding = env["torch"], env["synth"], env["binding"]
+    cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
+    lams = {B: torch.tensor(synth.draw_lambdas(B, seed=83), device="cuda") for B in (1, 4096)}
+    ref = {}
+    for B, lam in lams.items():
+        e = binding.DarkSirenLikelihood(cat, numerator="kde")
+        e.set_option("graph", 0)
+        ref[B] = e.loglike(lam)["logL"].clone()
+        torch.cuda.synchronize()
+        e.close()
+    lik = binding.DarkSirenLikelihood(cat, numerator="kde")
+    for B in (1, 4096, 1, 4096):
+        out = lik.loglike(lams[B])["logL"]
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(out, neginf=-1e300), torch.nan_to_num(ref[B], neginf=-1e300)), B
     lik.close()
