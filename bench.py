@@ -90,7 +90,7 @@ def cpu_baseline(cat, lam_row, grad, kde=None):
     import numpy as np
     import torch
     from oracle import dsl_oracle as O
-    n_ev = 40 if kde is None else 8
+    n_ev = 80 if kde is None else 16
     n_inj = 2_000_000
     sub = cat.subset(np.arange(n_ev), inj=slice(0, n_inj))
     t0 = time.perf_counter()
@@ -109,7 +109,7 @@ def cpu_baseline(cat, lam_row, grad, kde=None):
                      f"({sub.n_samp} samples) and first {n_inj} injections for 1 Lambda: {dt:.2f} s, "
                      f"scaled by {w_full}/{w_sub} sample-weights to one full-catalogue Lambda"}
     # the same oracle on one core, on a smaller sample
-    n_ev1, n_inj1 = (10, 250_000) if kde is None else (2, 250_000)
+    n_ev1, n_inj1 = (20, 250_000) if kde is None else (4, 250_000)
     sub1 = cat.subset(np.arange(n_ev1), inj=slice(0, n_inj1))
     nt = torch.get_num_threads()
     torch.set_num_threads(1)
