@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from tests.gpu_common import (TOL_LOGL_FP32, check_events, check_grad, log, need_gpu, rel_close)
+from tests.gpu_common import (TOL_GRAD, TOL_LOGL_FP32, check_events, check_grad, log, need_gpu, rel_close)
 
 pytestmark = pytest.mark.gpu
 
@@ -239,3 +239,63 @@ def test_config5_gradient(mods):
         assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32)
         check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
     lik.close()
+
+
+def test_config4_gradient_full_size(mods):
+    """Full-size O5-like catalogue, no gate (ln L smooth): the benchmark's launch
+    (FP32 weights, 64 points, adjoint) against the FP64 path's gradient on the
+    same points, and the FP64 gradient of the first point against central
+    differences of the FP64 ln L (33 points in one launch)."""
+    torch, synth, binding = mods["torch"], mods["synth"], mods["binding"]
+    log("[c4 full gradient: generate]")
+    cat = synth.make_catalog("c4")
+    lam = synth.lambdas_for("c4")
+    lt = torch.tensor(lam, device="cuda")
+    l32 = binding.DarkSirenLikelihood(cat, precision="fp32", gate_mode=2)
+    r32 = l32.loglike_grad(lt)
+    torch.cuda.synchronize()
+    g32, f32 = r32["grad"].cpu().numpy(), r32["logL"].cpu().numpy()
+    log(f"  fp32 tile {int(l32.info('lambda_tile_used'))}, chunk {int(l32.info('chunk'))}")
+    l32.close()
+    l64 = binding.DarkSirenLikelihood(cat, precision="fp64", gate_mode=2)
+    r64 = l64.loglike_grad(lt)
+    torch.cuda.synchronize()
+    g64, f64 = r64["grad"].cpu().numpy(), r64["logL"].cpu().numpy()
+    # The gradient is the small difference of two large sums (events, and N_det
+    # times the selection mean), so FP32 term errors of ~1e-5 are amplified
+    # entry by entry: the 1e-4 bound is relative to the gradient vector's norm,
+    # and each entry is held to 1e-3 of its own scale.
+    n_ok, worst_entry = 0, 0.0
+    for b in range(len(lam)):
+        if not math.isfinite(f64[b]):
+            assert not math.isfinite(f32[b]), b
+            continue
+        assert rel_close(float(f32[b]), float(f64[b]), TOL_LOGL_FP32), (b, f32[b], f64[b])
+        nrm = np.linalg.norm(g64[b])
+        assert np.linalg.norm(g32[b] - g64[b]) <= TOL_GRAD * nrm, (b, g32[b], g64[b])
+        scale = np.maximum(np.abs(g64[b]), 1e-2 * nrm)
+        entry = float(np.max(np.abs(g32[b] - g64[b]) / scale))
+        assert entry <= 10 * TOL_GRAD, (b, g32[b], g64[b])
+        worst_entry = max(worst_entry, entry)
+        n_ok += 1
+    log(f"  fp32 vs fp64: {n_ok} finite points within 1e-4 of the norm; worst entry {worst_entry:.2e} of its scale")
+    # central differences of the FP64 ln L around the first finite point
+    b0 = int(np.flatnonzero(np.isfinite(f64))[0])
+    lam0 = lam[b0]
+    hs = 1e-7 * np.maximum(np.abs(lam0), 1.0)
+    pts = [lam0]
+    for p in range(16):
+        for s in (1.0, -1.0):
+            x = lam0.copy()
+            x[p] += s * hs[p]
+            pts.append(x)
+    r = l64.loglike_grad(torch.tensor(np.stack(pts), device="cuda"))
+    torch.cuda.synchronize()
+    lnl = r["logL"].cpu().numpy()
+    g = r["grad"][0].cpu().numpy()
+    fd = np.array([(lnl[1 + 2 * p] - lnl[2 + 2 * p]) / (2 * hs[p]) for p in range(16)])
+    gn = np.linalg.norm(g)
+    bad = np.abs(fd - g) > 1e-5 * gn + 1e-4 * np.abs(g)
+    log(f"  fd max rel dev {np.max(np.abs(fd - g) / (1e-5 * gn + 1e-4 * np.abs(g))):.3f} of tolerance")
+    assert not bad.any(), [(synth.LAMBDA_NAMES[p], fd[p], g[p]) for p in np.flatnonzero(bad)]
+    l64.close()
