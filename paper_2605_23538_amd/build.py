@@ -19,7 +19,7 @@ def hipcc():
 
 def flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-            # packed FP32 ops are disabled for correctness on the test machines
+            # packed FP32 ops are disabled: some of their forms have given wrong results
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 
