@@ -137,8 +137,10 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     int kz = (int)xz;
     kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
     const T fz = xz - (T)kz;
-    l0 = (T)los[kz];
-    l1 = (T)los[kz + 1];
+    // both nodes in one load: the table's base stays scalar, the offset a 32-bit lane value
+    const float2 lp = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(los) + (uint32_t)kz * 4u);
+    l0 = (T)lp.x;
+    l1 = (T)lp.y;
     losv = l0 + fz * (l1 - l0);
   } else {
     losv = I * I * rE;
@@ -193,7 +195,7 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T rden = M::rcp(den);
   T lin = losv * mixf * rden;
   ok = ok && (lin == lin) && (lin < (T)3.0e38);
-  n_out = ok ? (int)En : R_SENTINEL;
+  n_out = GRAD ? (int)En : (ok ? (int)En : R_SENTINEL);   // (GRAD: only read where lin > 0)
   lin_out = ok ? lin : (T)0;
 
   if constexpr (GRAD) {
@@ -256,10 +258,12 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       int kg = (int)xg;
       kg = kg < 0 ? 0 : (kg > NWG - 1 ? NWG - 1 : kg);
       const T tg = xg - (T)kg;
-      const auto* wg = tv.wg;
-      const auto Ga = wg[(0 * (NWG + 1) + kg) * GL + lam], Gb = wg[(0 * (NWG + 1) + kg + 1) * GL + lam];
-      const auto Ha = wg[(1 * (NWG + 1) + kg) * GL + lam], Hb = wg[(1 * (NWG + 1) + kg + 1) * GL + lam];
-      const auto Ka = wg[(2 * (NWG + 1) + kg) * GL + lam], Kb = wg[(2 * (NWG + 1) + kg + 1) * GL + lam];
+      // one base address; the three tables and both nodes at constant offsets
+      constexpr int QS = (NWG + 1) * GL;
+      const auto* wg = tv.wg + kg * GL + lam;
+      const auto Ga = wg[0], Gb = wg[GL];
+      const auto Ha = wg[QS], Hb = wg[QS + GL];
+      const auto Ka = wg[2 * QS], Kb = wg[2 * QS + GL];
       drho_b = hermite<T>(tg, Ga.x, Ga.y, Gb.x, Gb.y);
       drho_mmin = hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
       drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
@@ -325,8 +329,13 @@ struct PixAcc {
   template <typename T>
   __device__ __forceinline__ void add(int n, T lin, const T* g) {
     if (lin > (T)0) {
-      if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
-      else if (n > R + RESCALE_MARGIN) rescale(n);
+      if constexpr (GRAD) {
+        // the first weight also takes this branch (R = R_SENTINEL): the zero sums stay zero
+        if (n > R + RESCALE_MARGIN) rescale(n);
+      } else {
+        if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
+        else if (n > R + RESCALE_MARGIN) rescale(n);
+      }
       const double W = ldexp((double)lin, n - R);
       S1 += W;
       S2 = fma(W, W, S2);
