@@ -83,8 +83,9 @@ enum { DSL_PRECISION_FP64 = 0, DSL_PRECISION_FP32 = 1 };
  * PE prior density in (m1_det, m2_det, d_L)).  Injections (n_inj detected out of
  * n_draw drawn): the same with ln_pdraw, the ln of the draw density.
  * Requirements: offsets start at 0, are non-decreasing and end at n_pix / n_samp;
- * 0 <= pix_los_row < n_los_rows; n_z >= 2; z_max > 0; masses and distances
- * finite and > 0; ln_pi / ln_pdraw finite; n_draw >= n_inj >= 1; n_events >= 1.
+ * 0 <= pix_los_row < n_los_rows; 2 <= n_z <= 2^24; z_max > 0; masses and
+ * distances finite and > 0; ln_pi / ln_pdraw finite; los and sky_z finite and
+ * >= 0; n_draw >= n_inj >= 1; 1 <= n_events < 2^31 - 1; n_pix < 2^31 - 1.
  * Violations return DSL_EINVAL.
  */
 typedef struct dsl_catalog_desc {

@@ -58,6 +58,9 @@ int hipfail(hipError_t e, const char* what) {
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;              // owns its allocation
+  DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -163,9 +166,14 @@ bool finite_all(const double* a, int64_t n) {
 int validate(const dsl_catalog_desc* d) {
   if (!d) return fail(DSL_EINVAL, "desc is NULL");
   if (d->n_events < 1 || !d->event_pix_off) return fail(DSL_EINVAL, "n_events < 1 or event_pix_off NULL");
+  // (before any array is read) event and pixel indices are 32-bit on the device
+  if (d->n_events >= (int64_t)INT32_MAX) return fail(DSL_EINVAL, "too many events");
+  if (d->n_pix >= (int64_t)INT32_MAX) return fail(DSL_EINVAL, "too many pixels");
   if (d->n_pix < 0 || !d->pix_samp_off || (d->n_pix > 0 && !d->pix_los_row))
     return fail(DSL_EINVAL, "pixel arrays missing");
   if (d->n_z < 2 || !(d->z_max > 0) || !std::isfinite(d->z_max)) return fail(DSL_EINVAL, "need n_z >= 2 and z_max > 0");
+  // table offsets inside a row are 32-bit byte offsets
+  if (d->n_z > (1 << 24)) return fail(DSL_EINVAL, "n_z must be <= 2^24");
   if (d->n_los_rows < 1 || !d->los || !d->sky_z) return fail(DSL_EINVAL, "LOS tables missing");
   if (d->n_samp < 0 || (d->n_samp > 0 && (!d->m1d || !d->m2d || !d->dl || !d->ln_pi)))
     return fail(DSL_EINVAL, "sample arrays missing");
@@ -185,7 +193,6 @@ int validate(const dsl_catalog_desc* d) {
     if (d->pix_los_row[j] < 0 || d->pix_los_row[j] >= d->n_los_rows)
       return fail(DSL_EINVAL, "pix_los_row out of range");
   }
-  if (d->n_pix >= (int64_t)INT32_MAX) return fail(DSL_EINVAL, "too many pixels");
   if (!finite_pos(d->m1d, d->n_samp) || !finite_pos(d->m2d, d->n_samp) || !finite_pos(d->dl, d->n_samp))
     return fail(DSL_EINVAL, "sample masses and distances must be finite and > 0");
   if (!finite_all(d->ln_pi, d->n_samp)) return fail(DSL_EINVAL, "ln_pi must be finite");
@@ -355,6 +362,7 @@ int build_items(dsl_handle* h, int64_t chunk) {
     w.s1 = std::min(h->n_inj, s + chunk);
     it.push_back(w);
   }
+  if (it.size() >= (size_t)INT32_MAX) return fail(DSL_EINVAL, "work list too long: use a larger chunk");
   std::vector<int32_t> ord(it.size());
   for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int32_t)i;
   auto cost = [&](int32_t i) { return (it[i].s1 - it[i].s0) + 4 * (int64_t)(it[i].pix1 - it[i].pix0); };

@@ -92,6 +92,9 @@ def test_null_arguments():
     ("n_inj", 0, "injection"),
     ("n_draw", 2, "n_draw"),
     ("n_z", 1, "n_z"),
+    ("n_z", (1 << 24) + 1, "2^24"),
+    ("n_events", 1 << 31, "too many events"),
+    ("n_pix", 1 << 31, "too many pixels"),
     ("precision", 7, "precision"),
     ("max_samples_per_pixel", -1, "max_samples_per_pixel"),
 ])
