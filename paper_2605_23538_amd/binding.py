@@ -169,8 +169,27 @@ class DarkSirenLikelihood:
             raise ValueError("lambda must have 16 columns")
         return lam.detach().to(device=f"cuda:{self.device}", dtype=torch.float64).contiguous()
 
+    @staticmethod
+    def _stream(stream, dev):
+        """The launch stream.  A stream other than the current one first waits for
+        the current stream, where the inputs and outputs were prepared; the
+        caller synchronises with it before reading the results."""
+        cur = torch.cuda.current_stream(dev)
+        if stream is None or stream == cur:
+            return cur, False
+        stream.wait_stream(cur)
+        return stream, True
+
+    @staticmethod
+    def _keep(tensors, stream):
+        # the caching allocator must not reuse these blocks before `stream` is done
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
     def loglike(self, lam: torch.Tensor, per_event: bool = False, stream=None):
-        """ln L for a [B, 16] batch; dict of device tensors."""
+        """ln L for a [B, 16] batch; dict of device tensors (written on `stream`,
+        default the current stream)."""
         lam = self._lam(lam)
         B = lam.shape[0]
         dev = lam.device
@@ -180,15 +199,18 @@ class DarkSirenLikelihood:
         if per_event:
             out["logL_event"] = torch.empty(B, self.n_events, dtype=torch.float64, device=dev)
             out["neff_event"] = torch.empty(B, self.n_events, dtype=torch.float64, device=dev)
-        st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+        s, side = self._stream(stream, dev)
         rc = self.lib.dsl_loglike(self.h, _ptr(lam), B, _ptr(out["logL"]), _ptr(out.get("logL_event")),
                                   _ptr(out.get("neff_event")), _ptr(out["neff_sel"]), _ptr(out["flags"]),
-                                  C.c_void_p(st))
+                                  C.c_void_p(s.cuda_stream))
+        if side:
+            self._keep([lam, *out.values()], s)
         _check(self.lib, rc, "dsl_loglike")
         return out
 
     def loglike_grad(self, lam: torch.Tensor, per_event: bool = False, stream=None):
-        """ln L and d ln L / d Lambda [B, 16] (adjoint sweep); dict of device tensors."""
+        """ln L and d ln L / d Lambda [B, 16] (adjoint sweep); dict of device tensors
+        (written on `stream`, default the current stream)."""
         lam = self._lam(lam)
         B = lam.shape[0]
         dev = lam.device
@@ -199,10 +221,12 @@ class DarkSirenLikelihood:
         if per_event:
             out["logL_event"] = torch.empty(B, self.n_events, dtype=torch.float64, device=dev)
             out["neff_event"] = torch.empty(B, self.n_events, dtype=torch.float64, device=dev)
-        st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+        s, side = self._stream(stream, dev)
         rc = self.lib.dsl_loglike_grad(self.h, _ptr(lam), B, _ptr(out["logL"]), _ptr(out["grad"]),
                                        _ptr(out.get("logL_event")), _ptr(out.get("neff_event")),
-                                       _ptr(out["neff_sel"]), _ptr(out["flags"]), C.c_void_p(st))
+                                       _ptr(out["neff_sel"]), _ptr(out["flags"]), C.c_void_p(s.cuda_stream))
+        if side:
+            self._keep([lam, *out.values()], s)
         _check(self.lib, rc, "dsl_loglike_grad")
         return out
 

@@ -146,6 +146,34 @@ def test_determinism_and_graph_replay(mods):
     lik.close()
 
 
+def test_side_stream(mods):
+    """Calls on a stream other than the current one (inputs prepared on the
+    current stream just before) equal calls on the current stream, with and
+    without graph replay."""
+    torch, synth = mods["torch"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    lam0 = torch.tensor(synth.draw_lambdas(32, seed=5), device="cuda")
+    ref = lik.loglike_grad(lam0)
+    ref_f = lik.loglike(lam0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    n = 0
+    for graph in (0, 1):
+        lik.set_option("graph", graph)
+        for rep in range(3):
+            lam = lam0 * 1.0   # written on the current stream right before the call
+            r = lik.loglike_grad(lam, stream=side)
+            f = lik.loglike(lam, stream=side)
+            side.synchronize()
+            for a, b in ((r["logL"], ref["logL"]), (f["logL"], ref_f["logL"])):
+                assert torch.equal(torch.nan_to_num(a, neginf=-1e300), torch.nan_to_num(b, neginf=-1e300))
+            assert torch.equal(r["grad"], ref["grad"])
+            n += 1
+    log(f"  {n} side-stream calls (graph off and on) equal current-stream calls")
+    lik.close()
+
+
 def test_graphs_after_workspace_growth(mods):
     """One handle, graph replay on, fixed output buffers per batch size, and
     batches that grow and shrink (workspace reallocations in between): every
