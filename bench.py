@@ -32,14 +32,18 @@ sys.path.insert(0, ROOT)
 # window, smoothing, exponent bookkeeping).
 FLOP_PER_WEIGHT_FWD = 175
 FLOP_PER_WEIGHT_GRAD = 300
-# KDE numerator: the weight without prior and rate (164, from the source); per
-# (sample, grid node) kernel term: difference, square, exp2, multiply-add (5); per
-# grid node of a (pixel, point) pair: position and trapezoid weight (3), prior
-# interpolation (5), rate psi(z)/(1+z) (1+z, log2, two exponents, two exp2, sum,
-# reciprocal: 9), products and scaled coordinate (3), the node's dot-product term (2).
+# KDE numerator: the weight without prior and rate (164, from the source).  Per
+# (sample, grid node) kernel term on a uniform grid, with the Gaussian's node-to-
+# node ratio recurrence: a multiply and an add, plus per sample and run of 16
+# nodes the start term (difference, square, exp2, weight) and the ratio (a
+# multiply) and the first add: 36 / 16, plus per sample and 256 nodes its own
+# ratio factor (5): 2.27.  Per grid node of a (pixel, point) pair: position and
+# trapezoid weight (3), prior interpolation (5), rate psi(z)/(1+z) (1+z, log2,
+# two exponents, two exp2, sum, reciprocal: 9), products (2), the recurrence's
+# node factor 2^(-(i S)^2) (4), the node's dot-product term (2).
 FLOP_PER_KDE_WEIGHT = 164
-FLOP_PER_KDE_NODE = 5
-FLOP_PER_KDE_GRID_NODE = 22
+FLOP_PER_KDE_NODE = 2.27
+FLOP_PER_KDE_GRID_NODE = 25
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6

@@ -100,8 +100,9 @@ __device__ __forceinline__ T rate_at(const LamC<T>& c, T z) {
 // weights without prior and rate, Eq. (8) sums, in-support redshift moments
 // and range.  Bandwidth from the in-support redshifts (order statistics in
 // ascending d_L order, which is ascending z for any point).  Pass B (each lane
-// holds 16 grid nodes of its point per block of 256 nodes): f(z_g) = sum_k w_k
-// exp(-(z_g - z_k)^2 / 2h^2) over the row's samples, then T = dz / (h sqrt(2
+// holds 16 consecutive grid nodes of its point per block of 256 nodes):
+// f(z_g) = sum_k w_k exp(-(z_g - z_k)^2 / 2h^2) over the row's samples (by the
+// node-to-node ratio recurrence of a Gaussian on a uniform grid), then T = dz / (h sqrt(2
 // pi)) * sum_g c_g p_LOS(z_g) rate(z_g) f(z_g) with trapezoid weights c_g.
 // Points of one tile (LT) share the block's tables.
 // FP32: 4 waves per SIMD (a few registers spill; measured faster than 3 waves
@@ -310,24 +311,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
       const double ga = fmax(0.0, (double)zlo - a.tau * h);
       const double gb = fmin(a.z_max, (double)zhi + a.tau * h);
       const double dz = (gb - ga) / (double)(a.n_grid - 1);
-      // coordinates scaled by sqrt(log2(e)/2)/h, so each term is exp2(-(x_g - x_k)^2)
+      // coordinates scaled by sqrt(log2(e)/2)/h and measured from ga, so each
+      // term is exp2(-(x_g - x_k)^2); S is the node spacing in these units
       const T invh = (T)(sqrt(0.5 * LOG2E) / h);
+      const T S = (T)(dz * (sqrt(0.5 * LOG2E) / h));
+      // Each lane holds NB consecutive nodes.  With x_g = x_0 + i S the terms
+      // of one sample follow t_i = u_i C_i, u_i = u_{i-1} P, C_i = 2^(-(i S)^2),
+      // P = 2^(-2 S (x_0 - x_k)), u_0 = w_k t_0: C_i goes into the node factor,
+      // so a term costs a multiply and an add.  u_i <= w_k 2^((NB-1)^2 S^2), and
+      // P is formed as 2^(-2 S x_0) 2^(2 S x_k) with both factors within
+      // 2^(+-2 S^2 (n_grid - 1)), so the recurrence is used while S <= 1/4 and
+      // 2 S^2 (n_grid - 1) <= 64 (row-uniform); wider spacings (a grid coarser
+      // than about a third of the bandwidth) evaluate every term.
+      const bool rec = S <= (T)0.25 && (T)2 * S * S * (T)(a.n_grid - 1) <= (T)64;
       // psi(z)/(1+z) = 1 / (2^(-(gamma-1) L) + 2^((kappa+1) L - (gamma+kappa) L_p)), L = log2(1+z)
       const T ra = -(c.gm3 + (T)2), rb = c.gk - (c.gm3 + (T)2), rc = -c.gk * c.Lp;
       const unsigned nz2 = (unsigned)(a.n_z - 2);
-      const double dz16 = 16.0 * dz;
       if (kl == 0 && a.evals && lo == 0) atomicAdd(&work[1], (unsigned long long)a.n_grid);
       for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
-        T zgs[NB], vg[NB];
-        // Node g = g0 + kl + 16 i.  Trapezoid weight min(max(n_grid - 1/2 - g, 0), 1):
+        T vg[NB];
+        // Node g = g0 + NB kl + i.  Trapezoid weight min(max(n_grid - 1/2 - g, 0), 1):
         // 1 inside, 1/2 at the last node, 0 past the end (the first node is halved below).
-        double zd = ga + (double)(g0 + kl) * dz;
-        const T cw = (T)a.n_grid - (T)0.5 - (T)(g0 + kl);
+        const int gl = g0 + NB * kl;
+        double zd = ga + (double)gl * dz;
+        const T cw = (T)a.n_grid - (T)0.5 - (T)gl;
+        const T x0l = (T)((double)gl * dz) * invh;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
           const T zg = (T)fmin(zd, a.z_max);
-          zd += dz16;
-          const T cg = fmin(fmax(cw - (T)(16 * i), (T)0), (T)1);
+          zd += dz;
+          const T cg = fmin(fmax(cw - (T)i, (T)0), (T)1);
           const T x = zg * inv_dz;   // zg >= 0
           unsigned k = (unsigned)x;
           k = k < nz2 ? k : nz2;
@@ -336,14 +349,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
           const T l0 = (T)rk[0], l1 = (T)rk[1];
           const T L = Mth<T>::log2((T)1 + zg);
           const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
-          vg[i] = cg * rate * (l0 + f * (l1 - l0));
-          zgs[i] = zg * invh;
+          const T iS = (T)i * S;
+          vg[i] = cg * rate * (l0 + f * (l1 - l0)) * (rec ? Mth<T>::exp2(-(iS * iS)) : (T)1);
         }
         if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
+        const T A = Mth<T>::exp2((T)-2 * S * x0l);
         for (int c0 = lo; c0 < hi; c0 += 16) {
           T z, w;
           z_w(c0, hi, z, w);
-          const T zsc = z * invh;
+          // out-of-support samples (z = -1) carry w = 0 and give exact zeros
+          const T zr = (z - (T)ga) * invh;
+          const T Bk = Mth<T>::exp2((T)2 * S * zr);
           const int cnt = hi - c0 < 16 ? hi - c0 : 16;
           if (g0 == 0) {
             const unsigned long long m = __ballot(w > (T)0);
@@ -353,17 +369,32 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
           T accf[NB];
 #pragma unroll
           for (int i = 0; i < NB; ++i) accf[i] = (T)0;
-          // zero weights (out of support) add exact zeros: no per-sample branch
           int j = 0;
-          do {   // cnt >= 1
-            const T wj = __shfl(w, j, 16);
-            const T zj = __shfl(zsc, j, 16);
+          if (rec) {
+            do {   // cnt >= 1
+              const T wj = __shfl(w, j, 16);
+              const T zj = __shfl(zr, j, 16);
+              const T P = A * __shfl(Bk, j, 16);
+              const T x0 = x0l - zj;
+              T u = wj * Mth<T>::exp2(-(x0 * x0));
+              accf[0] += u;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-              const T xx = zgs[i] - zj;
-              accf[i] = fma(wj, Mth<T>::exp2(-(xx * xx)), accf[i]);
-            }
-          } while (++j < cnt);
+              for (int i = 1; i < NB; ++i) {
+                u *= P;
+                accf[i] += u;
+              }
+            } while (++j < cnt);
+          } else {
+            do {
+              const T wj = __shfl(w, j, 16);
+              const T zj = __shfl(zr, j, 16);
+#pragma unroll
+              for (int i = 0; i < NB; ++i) {
+                const T xx = fma((T)i, S, x0l) - zj;
+                accf[i] = fma(wj, Mth<T>::exp2(-(xx * xx)), accf[i]);
+              }
+            } while (++j < cnt);
+          }
           // the lane's 16 positive terms of this chunk in T, the running sum in FP64
           T part = (T)0;
 #pragma unroll
