@@ -40,10 +40,11 @@ FLOP_PER_WEIGHT_GRAD = 300
 # ratio factor (5): 2.27.  Per grid node of a (pixel, point) pair: position and
 # trapezoid weight (3), prior interpolation (5), rate psi(z)/(1+z) (1+z, log2,
 # two exponents, two exp2, sum, reciprocal: 9), products (2), the recurrence's
-# node factor 2^(-(i S)^2) (4), the node's dot-product term (2).
+# node factor 2^(-(i S)^2) (itself by a ratio recurrence: 3), the node's
+# dot-product term (2).
 FLOP_PER_KDE_WEIGHT = 164
 FLOP_PER_KDE_NODE = 2.27
-FLOP_PER_KDE_GRID_NODE = 25
+FLOP_PER_KDE_GRID_NODE = 24
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6

@@ -336,21 +336,39 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
         double zd = ga + (double)gl * dz;
         const T cw = (T)a.n_grid - (T)0.5 - (T)gl;
         const T x0l = (T)((double)gl * dz) * invh;
+        // C_i = 2^(-(i S)^2) by C_{i+1} = C_i r_i, r_i = 2^(-(2i+1) S^2), r_{i+1} = r_i 2^(-2 S^2)
+        const T r0 = Mth<T>::exp2(-(S * S));
+        const T r2 = r0 * r0;
+        T Ci = (T)1, ri = r0;
+        // the table loads of LB nodes are issued before their arithmetic
+        constexpr int LB = 8;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          const T zg = (T)fmin(zd, a.z_max);
-          zd += dz;
-          const T cg = fmin(fmax(cw - (T)i, (T)0), (T)1);
-          const T x = zg * inv_dz;   // zg >= 0
-          unsigned k = (unsigned)x;
-          k = k < nz2 ? k : nz2;
-          const T f = x - (T)k;
-          const float* rk = row + k;
-          const T l0 = (T)rk[0], l1 = (T)rk[1];
-          const T L = Mth<T>::log2((T)1 + zg);
-          const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
-          const T iS = (T)i * S;
-          vg[i] = cg * rate * (l0 + f * (l1 - l0)) * (rec ? Mth<T>::exp2(-(iS * iS)) : (T)1);
+        for (int i0 = 0; i0 < NB; i0 += LB) {
+          float2 lp[LB];
+          T zgv[LB], fz[LB];
+#pragma unroll
+          for (int i = 0; i < LB; ++i) {
+            const T zg = (T)fmin(zd, a.z_max);
+            zd += dz;
+            const T x = zg * inv_dz;   // zg >= 0
+            unsigned k = (unsigned)x;
+            k = k < nz2 ? k : nz2;
+            zgv[i] = zg;
+            fz[i] = x - (T)k;
+            lp[i] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(row) + k * 4u);
+          }
+#pragma unroll
+          for (int i = 0; i < LB; ++i) {
+            const int ii = i0 + i;
+            const T zg = zgv[i];
+            const T cg = fmin(fmax(cw - (T)ii, (T)0), (T)1);
+            const T L = Mth<T>::log2((T)1 + zg);
+            const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
+            const T l0 = (T)lp[i].x, l1 = (T)lp[i].y;
+            vg[ii] = cg * rate * (l0 + fz[i] * (l1 - l0)) * (rec ? Ci : (T)1);
+            Ci *= ri;
+            ri *= r2;
+          }
         }
         if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
         const T A = Mth<T>::exp2((T)-2 * S * x0l);
