@@ -210,11 +210,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KdeWaves<T>
     bool pass;
     if (a.gate_mode == 2) pass = live && S1 > 0;
     else pass = live && S2 > 0 && S1 * S1 >= a.neff_min * S2;
-    sz = row_reduce(sz, [](double x, double y) { return x + y; });
-    szz = row_reduce(szz, [](double x, double y) { return x + y; });
-    zlo = row_reduce(zlo, [](T x, T y) { return fmin(x, y); });
-    zhi = row_reduce(zhi, [](T x, T y) { return fmax(x, y); });
-    const int nin = row_reduce(cin, [](int x, int y) { return x + y; });
+    // the in-support moments and range serve only the bandwidth of a passing
+    // row (pass is uniform over a row, and every reduction stays in its row)
+    int nin = 0;
+    if (pass) {
+      sz = row_reduce(sz, [](double x, double y) { return x + y; });
+      szz = row_reduce(szz, [](double x, double y) { return x + y; });
+      zlo = row_reduce(zlo, [](T x, T y) { return fmin(x, y); });
+      zhi = row_reduce(zhi, [](T x, T y) { return fmax(x, y); });
+      nin = row_reduce(cin, [](int x, int y) { return x + y; });
+    }
     // ---- bandwidth (Appendix D) from the n_in in-support redshifts of the row's point
     auto zs = [&](int r) -> double {   // r-th smallest in-support redshift
       const Samp<T> sp = samp[s0 + a.perm[s0 + r]];
