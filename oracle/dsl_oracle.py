@@ -264,7 +264,12 @@ def log_Z(m1, L: Lam):
     if float(L.delta_m.detach()) > 0.0:
         Zw = _window_integral(M.reshape(1), L)[0]
     else:
-        Zw = torch.zeros((), dtype=DT)
+        # Zero width: the window integral is mmin^beta * delta_m / 2 to first
+        # order (S(mmin + t dm) + S(mmin + (1-t) dm) = 1, so the window's mean
+        # over its width is 1/2).  Its value here is 0; the first-order term
+        # makes the derivative with respect to delta_m at the edge delta_m = 0
+        # of its domain the one-sided limit from delta_m > 0.
+        Zw = 0.5 * L.mmin ** L.beta * L.delta_m
     in_win = m1 < M
     up = torch.where(in_win, torch.clamp(m1, min=float(L.mmin.detach())), M + torch.zeros_like(m1))
     if float(L.delta_m.detach()) > 0.0:

@@ -463,6 +463,43 @@ def test_gradient_vs_central_differences():
         assert abs(fd - g[p]) <= 2e-6 * gn + 1e-5 * abs(g[p]), (synth.LAMBDA_NAMES[p], fd, g[p])
 
 
+def test_window_mean_is_one_half():
+    """The logistic window S(m_min + t dm) averages to 1/2 over its width (30-digit
+    quadrature), so the window integral is m_min^beta dm / 2 to first order in dm."""
+    mp.mp.dps = 30
+    f = lambda t: 1 / (1 + mp.e ** (1 / t + 1 / (t - 1)))
+    assert abs(mp.quad(f, [0, 0.5, 1]) - mp.mpf(1) / 2) < mp.mpf(10) ** -25
+    mmin, beta = 6.0, 2.5
+    for dm in (1e-3, 1e-4):
+        L = _L(mmin=mmin, delta_m=dm, beta=beta)
+        zw = float(O._window_integral(T([mmin + dm]), L)[0])
+        assert abs(zw / (0.5 * mmin ** beta * dm) - 1) < 2 * beta * dm / mmin
+
+
+@pytest.mark.parametrize("beta", [1.0, 9.25])
+def test_gradient_at_delta_m_zero(beta):
+    """delta_m = 0 is the edge of its domain: d ln L / d delta_m there is the
+    one-sided limit, checked against Richardson-extrapolated forward differences
+    of ln L; the other entries against central differences."""
+    cat = F.tiny_catalog()
+    base = dict(delta_m=0.0, mmin=6.0, beta=beta)
+    lam = synth.lam_vector(**base)
+    r0 = O.loglike(cat, lam, grad=True)
+    assert r0["flags"] == 0
+    g = r0["grad"]
+    gn = np.linalg.norm(g)
+    f = lambda **kw: O.loglike(cat, synth.lam_vector(**{**base, **kw}))["logL"]
+    D = lambda h: (f(delta_m=h) - r0["logL"]) / h
+    h = 1e-4
+    rich = 2 * D(h / 2) - D(h)
+    assert abs(rich - g[6]) <= 1e-6 * max(abs(g[6]), 1e-2 * gn), (rich, g[6])
+    for p in (0, 3, 4):
+        hp = 1e-6 * max(abs(lam[p]), 1.0)
+        name = synth.LAMBDA_NAMES[p]
+        fd = (f(**{name: lam[p] + hp}) - f(**{name: lam[p] - hp})) / (2 * hp)
+        assert abs(fd - g[p]) <= 2e-6 * gn + 1e-5 * abs(g[p]), (name, fd, g[p])
+
+
 # ---------------------------------------------------------------- spectral sirens
 def test_gaussian_toy_spectral():
     """Comoving-volume redshift prior, Omega_m = 0: I(z) = z, E = 1, so the prior
