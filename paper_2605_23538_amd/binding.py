@@ -259,7 +259,8 @@ class LogLFunction(torch.autograd.Function):
     def backward(ctx, g):
         (lam,) = ctx.saved_tensors
         r = ctx.lik.loglike_grad(lam)
-        grad = r["grad"] * g.to(r["grad"].dtype)[:, None]
+        grad = r["grad"] * g.to(device=r["grad"].device, dtype=r["grad"].dtype).reshape(-1)[:, None]
         if lam.dim() == 1:
             grad = grad[0]
-        return grad.to(lam.dtype), None
+        # the gradient goes back to the input's device and dtype (a CPU input is valid)
+        return grad.to(device=lam.device, dtype=lam.dtype), None

@@ -64,6 +64,7 @@ struct DevBuf {
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
+  bool fits(size_t bytes) const { return p && bytes <= n; }
   hipError_t ensure(size_t bytes) {
     if (bytes <= n && p) return hipSuccess;
     if (p) {
@@ -138,19 +139,41 @@ struct dsl_handle {
   int last_gl = 0;           // Lambda tile of the last call
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // setup | sweep | pixels | combine
   bool have_timing = false;
+  // recorded after each call's last launch: the host waits on it before it
+  // rewrites a device work list, moves a workspace buffer or drops a graph
+  // (the caller's stream may be non-blocking, so a synchronous copy on the
+  // null stream would not be ordered after that call's kernels)
+  hipEvent_t done = nullptr;
+  bool pending = false;
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::vector<const void*> ws_sig;   // workspace addresses the cached graphs were captured with
   std::map<std::pair<int, int>, SweepCfg> tuned;   // (B, grad) -> configuration
   ~dsl_handle() {
+    if (pending && done) (void)hipEventSynchronize(done);
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (done) (void)hipEventDestroy(done);
   }
 };
 
 namespace {
+
+// Wait until the last call on this handle has finished on the device.
+int quiesce(dsl_handle* h) {
+  if (h->pending) {
+    HIPCHK(hipEventSynchronize(h->done));
+    h->pending = false;
+  }
+  return DSL_OK;
+}
+
+void drop_graphs(dsl_handle* h) {
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+}
 
 bool finite_pos(const double* a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
@@ -306,6 +329,8 @@ int64_t auto_chunk(const dsl_handle* h, int GL) {
 // in event order; the processing order puts the largest items first.
 int build_items(dsl_handle* h, int64_t chunk) {
   if (chunk == h->built_chunk) return DSL_OK;
+  int rc0 = quiesce(h);   // the previous call may still read the current list
+  if (rc0) return rc0;
   std::vector<WorkItem> it;
   std::vector<SplitPix> sp;
   std::vector<int32_t> ev_off(h->n_events + 1, 0);
@@ -381,8 +406,7 @@ int build_items(dsl_handle* h, int64_t chunk) {
   h->inj_slot0 = inj0;
   h->inj_slot1 = (int)it.size();
   h->built_chunk = chunk;
-  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-  h->graphs.clear();
+  drop_graphs(h);
   return DSL_OK;
 }
 
@@ -455,6 +479,8 @@ int64_t kde_part_size(const dsl_handle* h, int B) {
 // replay, and a reallocation drops them through the workspace signature).
 int build_kde_parts(dsl_handle* h, int64_t P) {
   if (P == 0 || P == h->built_part_size) return DSL_OK;
+  int rc0 = quiesce(h);
+  if (rc0) return rc0;
   std::vector<KdePart> parts;
   std::vector<int64_t> ev_part(h->n_events + 1);
   for (int64_t e = 0; e < h->n_events; ++e) {
@@ -487,34 +513,80 @@ bool merge_events(const dsl_handle* h) {
   return h->numerator == 0 && h->n_events > 0 && h->inj_slot0 >= 16 * h->n_events;
 }
 
-int ensure_workspace(dsl_handle* h, int B, bool grad) {
+// Device workspace of one call: the handle's buffers, or (for the
+// allocation-free entry point) ranges of the per-device static scratch.
+struct Ws {
+  void* lamc = nullptr;
+  void* cos_tab = nullptr;
+  void* win_tab = nullptr;
+  void* wg_tab = nullptr;
+  void* valid = nullptr;
+  void* gmap = nullptr;
+  void* part = nullptr;
+  void* cpart = nullptr;
+  void* ev_rec = nullptr;
+  void* kde_out = nullptr;
+  void* kde_ev = nullptr;
+  void* kde_evals = nullptr;
+};
+
+// The workspace buffers of a call with B points: the handle's buffer, the
+// field of `ws` it fills, and its size.
+struct WsNeed {
+  DevBuf* buf;
+  void** dst;
+  size_t bytes;
+  const char* what;
+};
+
+struct WsNeeds {
+  WsNeed v[12];
+  int n = 0;
+  void add(DevBuf* b, void** d, size_t bytes, const char* what) { v[n++] = WsNeed{b, d, bytes, what}; }
+  const WsNeed* begin() const { return v; }
+  const WsNeed* end() const { return v + n; }
+};
+
+WsNeeds workspace_needs(dsl_handle* h, int B, bool grad, Ws& ws) {
   const int NU = h->fp32 ? NU_F32 : NU_F64, NW = h->fp32 ? NW_F32 : NW_F64;
+  const int NWG = h->fp32 ? NWG_F32 : NWG_F64;
   const size_t t1 = h->fp32 ? sizeof(float) : sizeof(double);
   const size_t lc = h->fp32 ? sizeof(LamC<float>) : sizeof(LamC<double>);
-  hipError_t e;
-  if ((e = h->lamc.ensure(lc * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (lamc)");
-  if ((e = h->cos_tab.ensure(2 * t1 * (NU + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (cos)");
-  if ((e = h->win_tab.ensure(2 * t1 * (NW + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (win)");
-  const int NWG = h->fp32 ? NWG_F32 : NWG_F64;
-  if ((e = h->wg_tab.ensure(6 * t1 * (NWG + 1) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (wg)");
-  if ((e = h->valid.ensure(sizeof(int) * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (valid)");
-  if ((e = h->gmap.ensure(sizeof(double) * N_GMAP * B)) != hipSuccess) return fail(DSL_ENOMEM, "workspace (gmap)");
   const size_t nf = grad ? NF_GRAD : NF_FWD;
-  if ((e = h->part.ensure(sizeof(double) * nf * (size_t)B * std::max(h->n_items, 1))) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (partials)");
-  if (h->numerator == 1 &&
-      (e = h->kde_out.ensure(sizeof(double) * NF_KDE * (size_t)B *
-                              std::max<int64_t>(kde_part_size(h, B) ? h->n_kde_parts : h->n_pix, 1))) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (KDE pixel terms)");
-  if ((e = h->cpart.ensure(sizeof(double) * NF_CSLICE * (size_t)B * combine_slices(h, B))) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (combine slices)");
-  if (merge_events(h) && (e = h->ev_rec.ensure(sizeof(double) * nf * (size_t)B * h->n_events)) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (event records)");
-  if (h->numerator == 1 && (e = h->kde_evals.ensure(2 * sizeof(unsigned long long))) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (KDE counter)");
-  if (h->numerator == 1 &&
-      (e = h->kde_ev.ensure(sizeof(double) * NF_KDE * (size_t)B * std::max<int64_t>(h->n_events, 1))) != hipSuccess)
-    return fail(DSL_ENOMEM, "workspace (KDE event terms)");
+  const size_t Bz = (size_t)B;
+  WsNeeds n;
+  n.add(&h->lamc, &ws.lamc, lc * Bz, "lamc");
+  n.add(&h->cos_tab, &ws.cos_tab, 2 * t1 * (NU + 1) * Bz, "cos");
+  n.add(&h->win_tab, &ws.win_tab, 2 * t1 * (NW + 1) * Bz, "win");
+  n.add(&h->wg_tab, &ws.wg_tab, 6 * t1 * (NWG + 1) * Bz, "wg");
+  n.add(&h->valid, &ws.valid, sizeof(int) * Bz, "valid");
+  n.add(&h->gmap, &ws.gmap, sizeof(double) * N_GMAP * Bz, "gmap");
+  n.add(&h->part, &ws.part, sizeof(double) * nf * Bz * (size_t)std::max(h->n_items, 1), "partials");
+  n.add(&h->cpart, &ws.cpart, sizeof(double) * NF_CSLICE * Bz * (size_t)combine_slices(h, B), "combine slices");
+  if (merge_events(h)) n.add(&h->ev_rec, &ws.ev_rec, sizeof(double) * nf * Bz * (size_t)h->n_events, "event records");
+  if (h->numerator == 1) {
+    const int64_t units = std::max<int64_t>(kde_part_size(h, B) ? h->n_kde_parts : h->n_pix, 1);
+    n.add(&h->kde_out, &ws.kde_out, sizeof(double) * NF_KDE * Bz * (size_t)units, "KDE pixel terms");
+    n.add(&h->kde_evals, &ws.kde_evals, 2 * sizeof(unsigned long long), "KDE counter");
+    n.add(&h->kde_ev, &ws.kde_ev, sizeof(double) * NF_KDE * Bz * (size_t)std::max<int64_t>(h->n_events, 1),
+          "KDE event terms");
+  }
+  return n;
+}
+
+// The handle's workspace for B points, grown when needed.
+int ensure_workspace(dsl_handle* h, int B, bool grad, Ws& ws) {
+  const WsNeeds need = workspace_needs(h, B, grad, ws);
+  bool grow = false;
+  for (const WsNeed& w : need) grow = grow || !w.buf->fits(w.bytes);
+  if (grow) {   // a buffer moves: the previous call must be done with it
+    const int rc = quiesce(h);
+    if (rc) return rc;
+  }
+  for (const WsNeed& w : need) {
+    if (w.buf->ensure(w.bytes) != hipSuccess) return fail(DSL_ENOMEM, std::string("workspace (") + w.what + ")");
+    *w.dst = w.buf->p;
+  }
   return DSL_OK;
 }
 
@@ -528,13 +600,13 @@ struct CallOut {
 };
 
 // Enqueue setup -> sweep -> combine on st (no synchronisation).
-int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& o, const SweepCfg& cfg,
-            hipStream_t st, bool timed) {
+int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool grad, const CallOut& o,
+            const SweepCfg& cfg, hipStream_t st, bool timed) {
   if (timed) HIPCHK(hipEventRecord(h->ev[0], st));
   // setup: two workgroups per point; wide ones shorten a call when they leave CUs free
   const int setup_threads = 2 * B < h->n_cu ? 1024 : 256;
-  HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, h->lamc.p, h->cos_tab.p, h->win_tab.p,
-                      grad ? h->wg_tab.p : nullptr, h->valid.as<int>(), grad ? h->gmap.as<double>() : nullptr,
+  HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, ws.lamc, ws.cos_tab, ws.win_tab,
+                      grad ? ws.wg_tab : nullptr, (int*)ws.valid, grad ? (double*)ws.gmap : nullptr,
                       setup_threads, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
   SweepArgs a;
@@ -549,16 +621,16 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   a.items = h->items.as<WorkItem>();
   a.order = h->order.as<int32_t>();
   a.n_items = h->n_items;
-  a.lamc = h->lamc.p;
-  a.cos_tab = h->cos_tab.p;
-  a.win_tab = h->win_tab.p;
-  a.win_grad_tab = h->wg_tab.p;
+  a.lamc = ws.lamc;
+  a.cos_tab = ws.cos_tab;
+  a.win_tab = ws.win_tab;
+  a.win_grad_tab = ws.wg_tab;
   a.B = B;
   a.neff_min = h->neff_min;
   a.gate_mode = h->gate_mode;
   a.z_prior = h->z_prior;
   a.skip_events = h->numerator == 1;
-  a.part = h->part.as<double>();
+  a.part = (double*)ws.part;
   const int n_tiles = (B + cfg.GL - 1) / cfg.GL;
   const int waves = cfg.waves;
   int grid_x = std::max(1, (h->n_cu * cfg.wg_per_cu + n_tiles - 1) / n_tiles);
@@ -566,7 +638,7 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   HIPCHK(launch_sweep(h->fp32, cfg.GL, grad, a, grid_x, 64 * waves, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[4], st));
   GateSplitArgs gs;
-  gs.part = h->part.as<double>();
+  gs.part = (double*)ws.part;
   gs.n_items = h->n_items;
   gs.nf = grad ? NF_GRAD : NF_FWD;
   gs.B = B;
@@ -588,27 +660,27 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
     k.parts = split ? h->kde_parts.as<KdePart>() : nullptr;
     k.n_parts = split ? h->n_kde_parts : h->n_pix;
     h->last_kde_units = k.n_parts;
-    k.lamc = h->lamc.p;
-    k.cos_tab = h->cos_tab.p;
-    k.win_tab = h->win_tab.p;
+    k.lamc = ws.lamc;
+    k.cos_tab = ws.cos_tab;
+    k.win_tab = ws.win_tab;
     k.B = B;
     k.bandwidth = h->kde_bandwidth;
     k.n_grid = h->kde_grid;
     k.tau = 5.0;
     k.neff_min = h->neff_min;
     k.gate_mode = h->gate_mode;
-    k.out = h->kde_out.as<double>();
-    k.evals = h->kde_evals.as<unsigned long long>();
+    k.out = (double*)ws.kde_out;
+    k.evals = (unsigned long long*)ws.kde_evals;
     HIPCHK(launch_kde(h->fp32, k, h->n_cu, st));
-    HIPCHK(launch_kde_events(h->kde_out.as<double>(), split ? h->ev_part_off.as<int64_t>() : h->ev_pix_off.as<int64_t>(),
+    HIPCHK(launch_kde_events((const double*)ws.kde_out, split ? h->ev_part_off.as<int64_t>() : h->ev_pix_off.as<int64_t>(),
                              k.n_parts, (int)h->n_events, B,
-                             h->kde_ev.as<double>(), st));
+                             (double*)ws.kde_ev, st));
   } else {
     HIPCHK(launch_gate_split(gs, st));
   }
   if (timed) HIPCHK(hipEventRecord(h->ev[2], st));
   CombineArgs c;
-  c.part = h->part.as<double>();
+  c.part = (const double*)ws.part;
   c.n_items = h->n_items;
   c.nf = grad ? NF_GRAD : NF_FWD;
   c.B = B;
@@ -620,18 +692,18 @@ int enqueue(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallO
   c.ln_ndraw = std::log((double)h->n_draw);
   c.neff_min = h->neff_min;
   c.gate_mode = h->gate_mode;
-  c.valid = h->valid.as<int>();
+  c.valid = (const int*)ws.valid;
   c.logL = o.logL;
   c.logL_event = o.logL_event;
   c.neff_event = o.neff_event;
   c.neff_sel = o.neff_sel;
   c.flags = o.flags;
   c.grad = o.grad;
-  c.gmap = h->gmap.as<double>();
-  c.kde = h->numerator == 1 ? h->kde_ev.as<double>() : nullptr;
-  c.ev_rec = merge_events(h) ? h->ev_rec.as<double>() : nullptr;
+  c.gmap = (const double*)ws.gmap;
+  c.kde = h->numerator == 1 ? (const double*)ws.kde_ev : nullptr;
+  c.ev_rec = merge_events(h) ? (double*)ws.ev_rec : nullptr;
   c.n_slices = combine_slices(h, B);
-  c.cpart = h->cpart.as<double>();
+  c.cpart = (double*)ws.cpart;
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -653,52 +725,60 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   int rc;
   if ((rc = build_items(h, cfg.chunk))) return rc;
   if (h->numerator == 1 && (rc = build_kde_parts(h, kde_part_size(h, B)))) return rc;
-  if ((rc = ensure_workspace(h, B, grad))) return rc;
+  Ws ws;
+  if ((rc = ensure_workspace(h, B, grad, ws))) return rc;
   // captured graphs hold workspace addresses: drop them all when any buffer moved
   const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
                                         h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
                                         h->ev_rec.p,  h->kde_parts.p, h->ev_part_off.p};
-  if (sig != h->ws_sig) {
-    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-    h->graphs.clear();
+  if (sig != h->ws_sig) {   // (a buffer that moved waited for the previous call first)
+    drop_graphs(h);
     h->ws_sig = sig;
   }
   if (h->timing) {
     h->have_timing = true;
-    return enqueue(h, d_lambda, B, grad, o, cfg, st, true);
-  }
-  if (!h->graph) return enqueue(h, d_lambda, B, grad, o, cfg, st, false);
-  GraphKey k{};
-  k.B = B;
-  k.grad = grad;
-  k.st = st;
-  const void* ptrs[8] = {d_lambda, o.logL, o.grad, o.logL_event, o.neff_event, o.neff_sel, o.flags,
-                         (const void*)(intptr_t)(((cfg.GL * 1000003 + cfg.chunk) * 64 + cfg.waves) * 8 + cfg.wg_per_cu)};
-  std::memcpy(k.ptrs, ptrs, sizeof(ptrs));
-  auto it = h->graphs.find(k);
-  if (it == h->graphs.end()) {
-    if (h->graphs.size() >= 16) {
-      for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-      h->graphs.clear();
+    rc = enqueue(h, ws, d_lambda, B, grad, o, cfg, st, true);
+  } else if (!h->graph) {
+    rc = enqueue(h, ws, d_lambda, B, grad, o, cfg, st, false);
+  } else {
+    GraphKey k{};
+    k.B = B;
+    k.grad = grad;
+    k.st = st;
+    const void* ptrs[8] = {d_lambda, o.logL, o.grad, o.logL_event, o.neff_event, o.neff_sel, o.flags,
+                           (const void*)(intptr_t)(((cfg.GL * 1000003 + cfg.chunk) * 64 + cfg.waves) * 8 + cfg.wg_per_cu)};
+    std::memcpy(k.ptrs, ptrs, sizeof(ptrs));
+    auto it = h->graphs.find(k);
+    if (it == h->graphs.end()) {
+      if (h->graphs.size() >= 16) {
+        if ((rc = quiesce(h))) return rc;
+        drop_graphs(h);
+      }
+      HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      rc = enqueue(h, ws, d_lambda, B, grad, o, cfg, h->cap_stream, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hipfail(e, "hipGraphInstantiate");
+      it = h->graphs.emplace(k, ex).first;
     }
-    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = enqueue(h, d_lambda, B, grad, o, cfg, h->cap_stream, false);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hipfail(e, "hipGraphInstantiate");
-    it = h->graphs.emplace(k, ex).first;
+    const hipError_t e = hipGraphLaunch(it->second, st);
+    rc = e == hipSuccess ? DSL_OK : hipfail(e, "hipGraphLaunch");
   }
-  HIPCHK(hipGraphLaunch(it->second, st));
-  return DSL_OK;
+  // marks the end of this call's work on st, also after a failed launch
+  // (whatever was enqueued before the failure must finish before the next rewrite)
+  const hipError_t er = hipEventRecord(h->done, st);
+  if (er == hipSuccess) h->pending = true;
+  if (rc) return rc;
+  return er == hipSuccess ? DSL_OK : hipfail(er, "hipEventRecord");
 }
 
 // Sweep configurations the autotuner may choose for batches of B points:
@@ -857,6 +937,7 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   if ((rc = pack_samples(h.get(), h->samp, d->m1d, d->m2d, d->dl, d->ln_pi, d->n_samp))) return rc;
   if ((rc = pack_samples(h.get(), h->inj, d->inj_m1d, d->inj_m2d, d->inj_dl, d->inj_ln_pdraw, d->n_inj))) return rc;
   for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIPCHK(init_kernel_attrs());
   HIPCHK(init_kde_attrs());
@@ -907,9 +988,10 @@ int dsl_set_option(dsl_handle* h, const char* key, double v) {
   } else {
     return fail(DSL_EINVAL, "unknown option '" + k + "'");
   }
-  // graphs bake in option values
-  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-  h->graphs.clear();
+  // graphs bake in option values (and may still be running)
+  const int rc = quiesce(h);
+  if (rc) return rc;
+  drop_graphs(h);
   return DSL_OK;
 }
 

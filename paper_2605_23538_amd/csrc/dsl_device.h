@@ -158,7 +158,8 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T mx = fmax(tP, fmax(tL, tH));
   // Conditional-mass normaliser over m1^(beta+1): rho (window table or closed form).
   const T t1 = (m1 - c.mmin) * c.inv_dm;
-  const bool inwin = t1 < (T)1;
+  // a window of zero width is a step at m_min: rho then has the closed form above M = m_min
+  const bool inwin = c.dm > (T)0 && t1 < (T)1;
   const T xw = t1 * (T)NW;
   int kw = (int)xw;
   kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);

@@ -255,7 +255,13 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
       run += (src[4 * j] + src[4 * j + 1]) + (src[4 * j + 2] + src[4 * j + 3]);
       dst[j + 1] = run;
     }
-    zw_s[tid] = win ? run / exp(s * log(M)) : 0.0;
+    // With delta_m = 0 the window integrals vanish, but two of their derivatives
+    // do not: the window integral of m^beta S is m_min^beta delta_m / 2 to first
+    // order (the window's mean over its width is 1/2), and the step at m_min
+    // moves with m_min.  Divided by M^s = m_min^(beta+1), the one-sided limits
+    // are d/d m_min -> -1/m_min and d/d delta_m -> -1/(2 m_min).
+    const double zw0 = (ok && dm == 0.0) ? (tid == 2 ? -1.0 / mmin : (tid == 3 ? -0.5 / mmin : 0.0)) : 0.0;
+    zw_s[tid] = win ? run / exp(s * log(M)) : zw0;
   }
   __syncthreads();
   // rho(t) = Z / (S m^s) and its t-derivative; gradient tables d rho / d(beta, m_min, dm).

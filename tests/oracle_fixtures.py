@@ -40,6 +40,8 @@ def toy_event_nodes(x, s, d_i, H0, mmin, n_gh=60, n_gl=2):
     for tk, wk in zip(t, wt):
         m1d = x + s * tk
         a, b = mmin * (1.0 + z), m1d
+        if b <= a:              # p1 vanishes below m_min: the node contributes nothing
+            continue
         for xl, wl in zip(xg, wg):
             m1.append(m1d)
             m2.append(0.5 * (b - a) * (xl + 1.0) + a)

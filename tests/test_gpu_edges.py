@@ -219,6 +219,11 @@ def test_autograd_function(mods):
     g = lam.grad.cpu().numpy()
     np.testing.assert_allclose(g[0], ref["grad"], rtol=1e-4, atol=1e-6 * np.linalg.norm(ref["grad"]))
     np.testing.assert_allclose(g[1], 2 * ref["grad"], rtol=1e-4, atol=2e-6 * np.linalg.norm(ref["grad"]))
+    # an input on the CPU: the value comes from the GPU, the gradient returns to the CPU
+    lam_cpu = torch.tensor(synth.fiducial_lambda(), dtype=torch.float64, requires_grad=True)
+    lik(lam_cpu).sum().backward()
+    assert lam_cpu.grad.device.type == "cpu" and lam_cpu.grad.shape == (16,)
+    np.testing.assert_allclose(lam_cpu.grad.numpy(), ref["grad"], rtol=1e-4, atol=1e-6 * np.linalg.norm(ref["grad"]))
     lik.close()
 
 
@@ -344,3 +349,108 @@ def test_maximum_batch(mods):
             assert rel_close(float(r["logL"][b]), ref["logL"], TOL_LOGL_FP32), b
             check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
     lik.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_delta_m_zero(mods, precision):
+    """delta_m = 0, a window of zero width (a step at m_min): ln L, per-event
+    values and the gradient against the oracle, whose delta_m entry there is
+    the one-sided derivative; the KDE numerator's value as well."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
+    lam = np.stack([synth.lam_vector(delta_m=0.0),
+                    synth.lam_vector(delta_m=0.0, mmin=6.0, beta=9.25, alpha=4.0),
+                    synth.lam_vector(delta_m=0.0, H0=55.0, Om=0.4, beta=-1.5, mmin=3.0)])
+    tol = TOL_LOGL_FP32 if precision == "fp32" else 1e-10
+    lik = mods["binding"].DarkSirenLikelihood(cat, precision=precision)
+    lt = torch.tensor(lam, device="cuda")
+    r = lik.loglike_grad(lt, per_event=True)
+    f = lik.loglike(lt)
+    torch.cuda.synchronize()
+    for b in range(len(lam)):
+        ref = O.loglike(cat, lam[b], grad=True, margins=True)
+        assert int(r["flags"][b]) == ref["flags"] == 0, (b, int(r["flags"][b]), ref["flags"])
+        assert rel_close(float(r["logL"][b]), ref["logL"], tol), (b, float(r["logL"][b]), ref["logL"])
+        assert float(f["logL"][b]) == float(r["logL"][b])
+        check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, tol)
+        check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
+    lik.close()
+    kde = mods["binding"].DarkSirenLikelihood(cat, precision=precision, numerator="kde")
+    rk = kde.loglike(lt[:1], per_event=True)
+    torch.cuda.synchronize()
+    ref = O.loglike_kde(cat, lam[0], margins=True)
+    assert int(rk["flags"][0]) == ref["flags"] == 0
+    assert rel_close(float(rk["logL"][0]), ref["logL"], tol)
+    kde.close()
+
+
+def test_side_stream_alternating_batches(mods):
+    """Calls on a non-blocking side stream, with no synchronisation between
+    them, alternating batches of 1 and 64 points: each change of batch size
+    rebuilds the work list for another item size while the previous call may
+    still run.  Every result equals an eager call on the current stream, with
+    graph replay off and on."""
+    torch, synth = mods["torch"], mods["synth"]
+    cat = synth.make_catalog("c2", n_events=30, n_inj=300_000)
+    lam = synth.draw_lambdas(64, seed=83)
+    lam[0] = synth.fiducial_lambda()
+    lt = torch.tensor(lam, device="cuda")
+    eager = mods["binding"].DarkSirenLikelihood(cat)
+    eager.set_option("graph", 0)
+    r64 = eager.loglike_grad(lt)
+    ref64 = r64["logL"].clone(), r64["grad"].clone()
+    ref1 = [eager.loglike(lt[i:i + 1])["logL"].clone() for i in range(4)]
+    torch.cuda.synchronize()
+    eager.close()
+    lik = mods["binding"].DarkSirenLikelihood(cat)
+    side = torch.cuda.Stream()
+    same = lambda a, b: torch.equal(torch.nan_to_num(a, neginf=-1e300), torch.nan_to_num(b, neginf=-1e300))
+    n = 0
+    for graph in (0, 1):
+        lik.set_option("graph", graph)
+        outs = []
+        for rep in range(3):
+            for i in range(4):
+                outs.append((i, lik.loglike(lt[i:i + 1], stream=side)))
+                outs.append((None, lik.loglike_grad(lt, stream=side)))
+        side.synchronize()
+        for i, r in outs:
+            if i is None:
+                assert same(r["logL"], ref64[0]) and torch.equal(r["grad"], ref64[1]), graph
+            else:
+                assert same(r["logL"], ref1[i]), (graph, i)
+            n += 1
+    log(f"  {n} unsynchronised side-stream calls alternating B = 1 and 64 equal eager calls")
+    lik.close()
+
+
+def test_downsampling_device_bytes(mods):
+    """A cap that binds (64 samples per pixel on a catalogue of about 125 per
+    pixel): the handle holds (dropped samples) x (32-byte record + 4-byte order
+    index) fewer bytes, and the capped likelihood equals the oracle's on the
+    catalogue downsampled by the same rule."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1")
+    full = mods["binding"].DarkSirenLikelihood(cat)
+    capped = mods["binding"].DarkSirenLikelihood(cat, max_samples_per_pixel=64, downsample_seed=7)
+    kept = int(capped.info("n_samp"))
+    ds = O.downsample(cat, 64, seed=7)
+    assert kept == ds.n_samp < cat.n_samp
+    assert int(capped.info("n_samp_input")) == cat.n_samp
+    drop = full.info("device_bytes") - capped.info("device_bytes")
+    assert drop == (cat.n_samp - kept) * (32 + 4), (drop, cat.n_samp, kept)
+    log(f"  kept {kept} of {cat.n_samp} samples; device bytes {full.info('device_bytes'):.0f} -> "
+        f"{capped.info('device_bytes'):.0f}")
+    lam = synth.fiducial_lambda()
+    r = capped.loglike(torch.tensor(lam[None], device="cuda"), per_event=True)
+    torch.cuda.synchronize()
+    ref = O.loglike(ds, lam, margins=True)
+    assert int(r["flags"][0]) == ref["flags"] == 0
+    assert rel_close(float(r["logL"][0]), ref["logL"], TOL_LOGL_FP32)
+    check_events(r["logL_event"][0].cpu().numpy(), r["neff_event"][0].cpu().numpy(), ref, TOL_LOGL_FP32)
+    # after a call the footprint still differs by at least the dropped records
+    full.loglike(torch.tensor(lam[None], device="cuda"))
+    torch.cuda.synchronize()
+    assert full.info("device_bytes") - capped.info("device_bytes") >= drop
+    full.close()
+    capped.close()
