@@ -380,7 +380,14 @@ class Options:
     z_prior: str = "los"        # "los" (pixel tables) or "comoving" (spectral sirens)
 
 
-def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
+def _block_tables(cat, pix):
+    """The LOS rows of a block's pixels in float64, and each pixel's row in it
+    (only the block's rows are converted, so the catalogue is streamed)."""
+    uniq, inv = np.unique(np.asarray(cat.pix_los_row)[pix], return_inverse=True)
+    return torch.from_numpy(np.asarray(cat.los[uniq], dtype=np.float64)), inv.astype(np.int64)
+
+
+def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
     """ln L_i, N_eff,i, pixel gate margins for a block of events."""
     p_lo = cat.event_pix_off[ev_ids]
     p_hi = cat.event_pix_off[ev_ids + 1]
@@ -390,7 +397,8 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, tables, margin_out=None):
     s_hi = cat.pix_samp_off[pix + 1]
     samp = np.concatenate([np.arange(a, b) for a, b in zip(s_lo, s_hi)]) if len(pix) else np.zeros(0, np.int64)
     pix_of_samp = np.repeat(np.arange(len(pix)), s_hi - s_lo)
-    rows = torch.from_numpy(cat.pix_los_row[pix].astype(np.int64))[torch.from_numpy(pix_of_samp)]
+    tables, prow = _block_tables(cat, pix)
+    rows = torch.from_numpy(prow)[torch.from_numpy(pix_of_samp)]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a[samp], dtype=np.float64))
     margins = [] if margin_out is not None else None
     lw = log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), tables, rows, cat.z_max, L, margins,
@@ -468,7 +476,6 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     opt = Options(neff_min=neff_min, gate_mode=gate_mode, z_prior=z_prior)
     lam_t = torch.tensor(lam_np, dtype=DT, requires_grad=grad)
     L = Lam.of(lam_t)
-    tables = torch.from_numpy(np.asarray(cat.los, dtype=np.float64))
     sky = torch.from_numpy(np.asarray(cat.sky_z, dtype=np.float64)).reshape(1, -1)
     g_ev = torch.zeros(16, dtype=DT)
     lnL_ev = np.empty(nE)
@@ -479,7 +486,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         ids = np.arange(b0, min(nE, b0 + event_block))
         mo = [] if margins else None
         with torch.set_grad_enabled(grad):
-            lnL_b, neff_b = _event_terms(cat, ids, L, opt, tables, mo)
+            lnL_b, neff_b = _event_terms(cat, ids, L, opt, mo)
             if grad and torch.isfinite(lnL_b).all():
                 g_ev += torch.autograd.grad(lnL_b.sum(), lam_t)[0]
         lnL_ev[ids] = lnL_b.detach().numpy()
@@ -692,7 +699,6 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
     bw = BANDWIDTHS[bandwidth]
     lam_t = torch.tensor(lam_np, dtype=DT, requires_grad=grad)
     L = Lam.of(lam_t)
-    tables = torch.from_numpy(np.asarray(cat.los, dtype=np.float64))
     sky = torch.from_numpy(np.asarray(cat.sky_z, dtype=np.float64)).reshape(1, -1)
     log_nmin = math.log(neff_min) if neff_min > 0 else -math.inf
     lnL_ev = np.empty(nE)
@@ -725,8 +731,8 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
                 if not math.isfinite(float(l1)) or (gate_mode != 2 and lneff < log_nmin):
                     continue
                 h = bw(z)
-                lT.append(_pixel_kde_term(z, lw, h, tables[int(cat.pix_los_row[j])].reshape(1, -1), cat.z_max,
-                                          L, n_grid))
+                table = torch.from_numpy(np.asarray(cat.los[int(cat.pix_los_row[j])], dtype=np.float64))
+                lT.append(_pixel_kde_term(z, lw, h, table.reshape(1, -1), cat.z_max, L, n_grid))
                 lS1.append(l1)
                 lS2.append(l2)
             if lT:
