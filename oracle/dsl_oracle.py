@@ -378,6 +378,7 @@ class Options:
     neff_min: float = 2.0
     gate_mode: int = 0          # 0: per-pixel gate; 1: also per-event gate; 2: none
     z_prior: str = "los"        # "los" (pixel tables) or "comoving" (spectral sirens)
+    gate_flip: Optional[np.ndarray] = None   # sorted pixel ids whose gate decision is inverted
 
 
 def _block_tables(cat, pix):
@@ -414,6 +415,11 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
         passing = finite
     else:
         passing = finite & (lneff.detach() >= log_nmin)
+        if opt.gate_flip is not None and len(opt.gate_flip):
+            # the other outcome of the Eq. (8) test for the listed pixels: the
+            # decisions a path in another precision may take near the threshold
+            flip = torch.from_numpy(np.isin(pix, opt.gate_flip))
+            passing = torch.where(flip, finite & ~passing, passing)
     ev_seg = torch.from_numpy(ev_of_pix)
     neg = torch.full_like(lS1, -math.inf)
     lS1p = torch.where(passing, lS1, neg)
@@ -439,7 +445,7 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
             sm = margins[0] if margins else torch.zeros(0, dtype=DT)
             smp = torch.full((n_p,), math.inf, dtype=DT).scatter_reduce(0, seg, sm, "amin")
             ev_samp = torch.full((nE,), math.inf, dtype=DT).scatter_reduce(0, ev_seg, smp, "amin")
-            margin_out.append((ev_gate.numpy(), ev_samp.numpy()))
+            margin_out.append((ev_gate.numpy(), ev_samp.numpy(), pix, gm.numpy()))
     return lnL, neff_ev
 
 
@@ -456,7 +462,8 @@ def _selection_chunk(cat, sl, L: Lam, sky, margin_out=None, z_prior="los"):
 
 
 def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = False,
-            event_block: int = 64, inj_chunk: int = 1 << 20, margins: bool = False, z_prior: str = "los"):
+            event_block: int = 64, inj_chunk: int = 1 << 20, margins: bool = False, z_prior: str = "los",
+            gate_flip=None):
     """Oracle log-likelihood of one hyperparameter point.
 
     Returns a dict with logL, logL_event[n_events], neff_event[n_events],
@@ -464,7 +471,10 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     margins=True it also reports, per event, the smallest |ln N_eff - ln N_min|
     over its pixels and the smallest relative distance of a sample to a
     support edge (d_L(z_max), m_max), for parity tests that must allow for
-    decisions taken in another precision.
+    decisions taken in another precision, and pixel_gate_margin[n_pix], that
+    distance for every pixel (inf for a pixel without weight).  gate_flip (pixel
+    ids) inverts the gate decision of those pixels, so such a test can evaluate
+    the other outcome.
     """
     lam_np = np.asarray(lam, dtype=np.float64).reshape(16)
     nE = cat.n_events
@@ -473,7 +483,8 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     if not lambda_is_valid(lam_np):
         out["flags"] = FLAG_INVALID_LAMBDA
         return out
-    opt = Options(neff_min=neff_min, gate_mode=gate_mode, z_prior=z_prior)
+    flips = None if gate_flip is None else np.unique(np.asarray(gate_flip, dtype=np.int64))
+    opt = Options(neff_min=neff_min, gate_mode=gate_mode, z_prior=z_prior, gate_flip=flips)
     lam_t = torch.tensor(lam_np, dtype=DT, requires_grad=grad)
     L = Lam.of(lam_t)
     sky = torch.from_numpy(np.asarray(cat.sky_z, dtype=np.float64)).reshape(1, -1)
@@ -482,6 +493,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     neff_ev = np.empty(nE)
     gate_m = np.empty(nE)
     samp_m = np.empty(nE)
+    pix_m = np.full(cat.n_pix, math.inf) if margins else None
     for b0 in range(0, nE, event_block):
         ids = np.arange(b0, min(nE, b0 + event_block))
         mo = [] if margins else None
@@ -492,7 +504,8 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         lnL_ev[ids] = lnL_b.detach().numpy()
         neff_ev[ids] = neff_b.numpy()
         if margins:
-            gate_m[ids], samp_m[ids] = mo[0]
+            gate_m[ids], samp_m[ids], pix_b, pm_b = mo[0]
+            pix_m[pix_b] = pm_b
     # Selection term: alpha = (1/N_draw) sum_n w_n, merged over chunks.
     lc1, lc2, gc = [], [], []
     inj_margin = math.inf
@@ -532,6 +545,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         out["gate_margin"] = gate_m
         out["sample_margin"] = samp_m
         out["inj_margin"] = inj_margin
+        out["pixel_gate_margin"] = pix_m
     return out
 
 

@@ -283,8 +283,10 @@ def test_monte_carlo_jacobian():
 
 
 # ---------------------------------------------------------------- brute force
-def _mp_loglike(cat, lam, neff_min=2.0):
-    """The definition evaluated with 30-digit mpmath (tanh-sinh, findroot)."""
+def _mp_loglike(cat, lam, neff_min=2.0, flip=(), neff_out=None):
+    """The definition evaluated with 30-digit mpmath (tanh-sinh, findroot); the
+    gate decisions of the pixels in `flip` are inverted; neff_out collects every
+    pixel's N_eff."""
     mp.mp.dps = 30
     H0, Om, a, b, mmin, mmax, dm, mul, sl, muh, sh, lg, ll, gam, kap, zp = [mp.mpf(float(x)) for x in lam]
     c = mp.mpf(C)
@@ -339,7 +341,12 @@ def _mp_loglike(cat, lam, neff_min=2.0):
                   for k in range(cat.pix_samp_off[p], cat.pix_samp_off[p + 1])]
             n_s += len(ws)
             s1, s2 = sum(ws), sum(w * w for w in ws)
-            if s2 > 0 and s1 * s1 / s2 >= neff_min:
+            passes = s2 > 0 and s1 * s1 / s2 >= neff_min
+            if neff_out is not None:
+                neff_out.append(s1 * s1 / s2 if s2 > 0 else mp.mpf(0))
+            if p in flip and s1 > 0:
+                passes = not passes
+            if passes:
                 S1p += s1
         lnL_ev.append(mp.log(S1p / n_s))
     alpha = sum(weight(cat.inj_m1d[n], cat.inj_m2d[n], cat.inj_dl[n], cat.inj_ln_pdraw[n], cat.sky_z)
@@ -359,6 +366,24 @@ def test_bruteforce_mpmath(lam_kw, neff_min):
     np.testing.assert_allclose(r["logL_event"], ev, rtol=1e-12, atol=1e-12)
     assert abs(r["ln_alpha"] - la) < 1e-12
     np.testing.assert_allclose([r["logL"]], [tot], rtol=1e-12)
+
+
+@pytest.mark.parametrize("flip", [[0], [1, 2], [3]])
+def test_gate_flip_and_pixel_margins_bruteforce(flip):
+    """The oracle's other-outcome hook (a path in another precision may decide
+    a pixel near the N_eff threshold the other way) and its per-pixel gate
+    margins, against the 30-digit definition with the same decisions inverted."""
+    cat = F.tiny_catalog()
+    lam = synth.lam_vector(H0=45.0, Om=0.45, delta_m=8.0, beta=-2.0, z_p=0.5, gamma=5.0)
+    neff = []
+    ev, la, tot = _mp_loglike(cat, lam, 2.0, flip=set(flip), neff_out=neff)
+    r = O.loglike(cat, lam, gate_flip=flip, margins=True)
+    np.testing.assert_allclose(r["logL_event"], ev, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose([r["logL"]], [tot], rtol=1e-12)
+    base = O.loglike(cat, lam)
+    assert not np.allclose(base["logL_event"], r["logL_event"], rtol=1e-9, atol=0)
+    want = [abs(float(mp.log(n)) - math.log(2.0)) for n in neff]
+    np.testing.assert_allclose(r["pixel_gate_margin"], want, rtol=1e-9, atol=1e-12)
 
 
 # ---------------------------------------------------------------- invariances
