@@ -79,6 +79,10 @@ enum { DSL_PRECISION_FP64 = 0, DSL_PRECISION_FP32 = 1 };
  *   los[n_los_rows * n_z]      redshift prior tables, row-major, on n_z uniform
  *                              nodes over [0, z_max] (linearly interpolated, zero outside)
  *   sky_z[n_z]                 sky-averaged redshift prior (selection term)
+ * The tables are given either in float32 (los, sky_z) or in float64 (los_f64,
+ * sky_z_f64): exactly one pointer of each pair is non-NULL.  They are converted
+ * at upload to the precision of the handle (float32 for DSL_PRECISION_FP32,
+ * float64 for DSL_PRECISION_FP64), so an FP64 handle keeps float64 tables.
  * Samples (n_samp, detector frame): m1d, m2d [Msun], dl [Mpc], ln_pi (ln of the
  * PE prior density in (m1_det, m2_det, d_L)).  Injections (n_inj detected out of
  * n_draw drawn): the same with ln_pdraw, the ln of the draw density.
@@ -97,8 +101,10 @@ typedef struct dsl_catalog_desc {
   int64_t n_los_rows;
   int32_t n_z;
   double z_max;
-  const float* los;
-  const float* sky_z;
+  const float* los;        /* float32 tables, or NULL when los_f64 is given */
+  const float* sky_z;      /* float32 sky table, or NULL when sky_z_f64 is given */
+  const double* los_f64;   /* float64 tables, or NULL when los is given */
+  const double* sky_z_f64; /* float64 sky table, or NULL when sky_z is given */
   int64_t n_samp;
   const double* m1d;
   const double* m2d;
@@ -165,6 +171,7 @@ int dsl_set_option(dsl_handle* h, const char* key, double value);
 /* Read back an option or a catalogue size ("n_events", "n_pix", "n_samp",
  * "n_inj", "n_items", "precision", ...), "lambda_tile_used" (the Lambda tile
  * of the last call), "device_bytes" (device memory the handle holds),
+ * "work_list_bytes" (of it, the work list: items, order, event offsets, split pixels),
  * "kde_evals" and "kde_nodes" (of the last call with the KDE numerator: the
  * (sample, grid node) kernel terms and the grid nodes evaluated; both wait for
  * the device), "kde_units" (the grid-stage units of that call: n_pix, or more
@@ -175,7 +182,10 @@ int dsl_set_option(dsl_handle* h, const char* key, double value);
 int dsl_get_info(dsl_handle* h, const char* key, double* value);
 
 /*
- * Log-likelihood of B points.
+ * Log-likelihood of B points (Sec. II A: Eq. 1 for z(d_L), Eq. 7 for the
+ * per-sample weights, Eq. 8 for the pixel gate, Eq. 5 for the per-event Monte
+ * Carlo sums and the selection term, Eq. 3 for ln L), one persistent sweep
+ * for the whole batch: every sample record is read once for all B points.
  *   d_lambda     [B][16] device, layout above
  *   d_logL       [B] device, ln L (or -inf with a flag)
  *   d_logL_event [B][n_events] device or NULL: ln L_i
@@ -193,10 +203,13 @@ int dsl_loglike(dsl_handle* h, const double* d_lambda, int B, double* d_logL,
 /*
  * Log-likelihood and its gradient d ln L / d Lambda (all 16 entries) for B
  * points, by an adjoint sweep that recomputes every per-sample weight and its
- * derivatives (nothing is stored between calls).  Gates and supports are held
- * at their current state (derivative almost everywhere); entries of a point
- * whose ln L is -inf are 0.
- *   d_grad [B][16] device.  Other arguments as in dsl_loglike.
+ * derivatives (nothing is stored between calls): the derivative of Eq. 3 through
+ * Eqs. 5 and 7, with z(d_L) of Eq. 1 differentiated implicitly,
+ *   d ln L = sum_i <d ln w>_(w, passing pixels of i) - N_det <d ln w>_(w, injections).
+ * Gates and supports are held at their current state (derivative almost
+ * everywhere); entries of a point whose ln L is -inf are 0.
+ *   d_grad [B][16] device.  Other arguments as in dsl_loglike; the per-event
+ *   outputs (d_logL_event, d_neff_event, d_neff_sel) are the same as there.
  */
 int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_logL,
                      double* d_grad, double* d_logL_event, double* d_neff_event,

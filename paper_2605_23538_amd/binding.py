@@ -34,7 +34,7 @@ class CatalogDesc(C.Structure):
         ("n_events", C.c_int64), ("event_pix_off", C.c_void_p),
         ("n_pix", C.c_int64), ("pix_samp_off", C.c_void_p), ("pix_los_row", C.c_void_p),
         ("n_los_rows", C.c_int64), ("n_z", C.c_int32), ("z_max", C.c_double),
-        ("los", C.c_void_p), ("sky_z", C.c_void_p),
+        ("los", C.c_void_p), ("sky_z", C.c_void_p), ("los_f64", C.c_void_p), ("sky_z_f64", C.c_void_p),
         ("n_samp", C.c_int64), ("m1d", C.c_void_p), ("m2d", C.c_void_p), ("dl", C.c_void_p),
         ("ln_pi", C.c_void_p),
         ("n_inj", C.c_int64), ("inj_m1d", C.c_void_p), ("inj_m2d", C.c_void_p), ("inj_dl", C.c_void_p),
@@ -115,10 +115,14 @@ class DarkSirenLikelihood:
         prec = {"fp32": DSL_PRECISION_FP32, "fp64": DSL_PRECISION_FP64}[precision]
         self.precision = precision
         self.n_events = int(catalog.n_events)
+        # redshift-prior tables go over in their own precision (float64 or float32);
+        # the library converts them to the handle's
+        tdt = np.float64 if np.asarray(catalog.los).dtype == np.float64 else np.float32
+        sdt = np.float64 if np.asarray(catalog.sky_z).dtype == np.float64 else np.float32
         keep = dict(
             epo=_np(catalog.event_pix_off, np.int64), pso=_np(catalog.pix_samp_off, np.int64),
-            row=_np(catalog.pix_los_row, np.int32), los=_np(catalog.los, np.float32),
-            sky=_np(catalog.sky_z, np.float32), m1=_np(catalog.m1d, np.float64), m2=_np(catalog.m2d, np.float64),
+            row=_np(catalog.pix_los_row, np.int32), los=_np(catalog.los, tdt),
+            sky=_np(catalog.sky_z, sdt), m1=_np(catalog.m1d, np.float64), m2=_np(catalog.m2d, np.float64),
             dl=_np(catalog.dl, np.float64), lp=_np(catalog.ln_pi, np.float64),
             im1=_np(catalog.inj_m1d, np.float64), im2=_np(catalog.inj_m2d, np.float64),
             idl=_np(catalog.inj_dl, np.float64), ilp=_np(catalog.inj_ln_pdraw, np.float64))
@@ -126,7 +130,10 @@ class DarkSirenLikelihood:
         d = CatalogDesc(
             n_events=self.n_events, event_pix_off=p(keep["epo"]), n_pix=len(keep["pso"]) - 1,
             pix_samp_off=p(keep["pso"]), pix_los_row=p(keep["row"]), n_los_rows=keep["los"].shape[0],
-            n_z=keep["los"].shape[1], z_max=float(catalog.z_max), los=p(keep["los"]), sky_z=p(keep["sky"]),
+            n_z=keep["los"].shape[1], z_max=float(catalog.z_max),
+            los=p(keep["los"]) if tdt == np.float32 else None, sky_z=p(keep["sky"]) if sdt == np.float32 else None,
+            los_f64=p(keep["los"]) if tdt == np.float64 else None,
+            sky_z_f64=p(keep["sky"]) if sdt == np.float64 else None,
             n_samp=len(keep["m1"]), m1d=p(keep["m1"]), m2d=p(keep["m2"]), dl=p(keep["dl"]), ln_pi=p(keep["lp"]),
             n_inj=len(keep["im1"]), inj_m1d=p(keep["im1"]), inj_m2d=p(keep["im2"]), inj_dl=p(keep["idl"]),
             inj_ln_pdraw=p(keep["ilp"]), n_draw=int(catalog.n_draw), precision=prec,

@@ -24,7 +24,8 @@ size_t sweep_lds_bytes(int fp32, int GL, bool grad);
 hipError_t launch_pack(int fp32, const double* m1, const double* m2, const double* dl, const double* lnp,
                        int64_t n, void* out, hipStream_t st);
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, int threads, hipStream_t st);
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* cos64, int threads,
+                        hipStream_t st);
 hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
@@ -115,7 +116,7 @@ struct dsl_handle {
   DevBuf samp, inj, pix_off, pix_row, los, sky, ln_ns;
   // KDE numerator: pixel parts and event -> parts (split grid stage), event ->
   // pixels, per-pixel d_L order
-  DevBuf kde_parts, ev_part_off, ev_pix_off, perm;
+  DevBuf kde_parts, ev_part_off, ev_pix_off, perm, kde_order;
   int64_t n_kde_parts = 0, built_part_size = 0, max_pix_samples = 0;
   int64_t last_kde_units = 0;   // grid-stage units of the last KDE call (pixels or pixel parts)
   // work list (for the current chunk size)
@@ -123,7 +124,7 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, kde_out, kde_ev, kde_evals, cpart, ev_rec;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, cos64, kde_out, kde_ev, kde_evals, cpart, ev_rec;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -197,7 +198,8 @@ int validate(const dsl_catalog_desc* d) {
   if (d->n_z < 2 || !(d->z_max > 0) || !std::isfinite(d->z_max)) return fail(DSL_EINVAL, "need n_z >= 2 and z_max > 0");
   // table offsets inside a row are 32-bit byte offsets
   if (d->n_z > (1 << 24)) return fail(DSL_EINVAL, "n_z must be <= 2^24");
-  if (d->n_los_rows < 1 || !d->los || !d->sky_z) return fail(DSL_EINVAL, "LOS tables missing");
+  if (d->n_los_rows < 1 || (!d->los == !d->los_f64) || (!d->sky_z == !d->sky_z_f64))
+    return fail(DSL_EINVAL, "give exactly one of los / los_f64 and one of sky_z / sky_z_f64");
   if (d->n_samp < 0 || (d->n_samp > 0 && (!d->m1d || !d->m2d || !d->dl || !d->ln_pi)))
     return fail(DSL_EINVAL, "sample arrays missing");
   if (d->n_inj < 1 || !d->inj_m1d || !d->inj_m2d || !d->inj_dl || !d->inj_ln_pdraw)
@@ -223,10 +225,15 @@ int validate(const dsl_catalog_desc* d) {
     return fail(DSL_EINVAL, "injection masses and distances must be finite and > 0");
   if (!finite_all(d->inj_ln_pdraw, d->n_inj)) return fail(DSL_EINVAL, "inj_ln_pdraw must be finite");
   const int64_t nl = d->n_los_rows * (int64_t)d->n_z;
-  for (int64_t i = 0; i < nl; ++i)
-    if (!std::isfinite(d->los[i]) || d->los[i] < 0) return fail(DSL_EINVAL, "LOS tables must be finite and >= 0");
-  for (int i = 0; i < d->n_z; ++i)
-    if (!std::isfinite(d->sky_z[i]) || d->sky_z[i] < 0) return fail(DSL_EINVAL, "sky_z must be finite and >= 0");
+  auto tab_ok = [](const float* f, const double* g, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+      const double v = f ? (double)f[i] : g[i];
+      if (!std::isfinite(v) || v < 0) return false;
+    }
+    return true;
+  };
+  if (!tab_ok(d->los, d->los_f64, nl)) return fail(DSL_EINVAL, "LOS tables must be finite and >= 0");
+  if (!tab_ok(d->sky_z, d->sky_z_f64, d->n_z)) return fail(DSL_EINVAL, "sky_z must be finite and >= 0");
   return DSL_OK;
 }
 
@@ -285,6 +292,30 @@ int upload(DevBuf& b, const void* src, size_t bytes) {
   hipError_t e = b.ensure(bytes);
   if (e != hipSuccess) return fail(DSL_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   if (bytes && src) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  return DSL_OK;
+}
+
+// Redshift-prior tables in the handle's precision (float32 for FP32 handles,
+// float64 for FP64 ones) from float32 or float64 input; a conversion goes
+// through a host staging slice, so a 10 GB catalogue needs no second copy.
+int upload_table(dsl_handle* h, DevBuf& b, const float* f32, const double* f64, int64_t n) {
+  const size_t el = h->fp32 ? sizeof(float) : sizeof(double);
+  if ((h->fp32 && f32) || (!h->fp32 && f64)) return upload(b, f32 ? (const void*)f32 : (const void*)f64, el * n);
+  int rc = upload(b, nullptr, el * (size_t)n);
+  if (rc) return rc;
+  const int64_t slice = 1 << 22;
+  std::vector<float> sf(h->fp32 ? (size_t)std::min(n, slice) : 0);
+  std::vector<double> sd(h->fp32 ? 0 : (size_t)std::min(n, slice));
+  for (int64_t i0 = 0; i0 < n; i0 += slice) {
+    const int64_t m = std::min(slice, n - i0);
+    if (h->fp32) {
+      for (int64_t i = 0; i < m; ++i) sf[i] = (float)f64[i0 + i];
+      HIPCHK(hipMemcpy(b.as<float>() + i0, sf.data(), sizeof(float) * m, hipMemcpyHostToDevice));
+    } else {
+      for (int64_t i = 0; i < m; ++i) sd[i] = (double)f32[i0 + i];
+      HIPCHK(hipMemcpy(b.as<double>() + i0, sd.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+    }
+  }
   return DSL_OK;
 }
 
@@ -464,11 +495,13 @@ int combine_slices(const dsl_handle* h, int B) {
   return std::max(1, std::min(32, std::min(by_items, by_cu)));
 }
 
-// Part size of the KDE grid stage for batches of B points: a pixel holding more
-// than half the samples a wavefront handles on average over the launch would be
-// a long tail, so pixels above max(KDE_PART, that half) are split into parts of
-// that many samples (a multiple of 16).  0: no pixel is split.
+// Part size of the KDE grid stage for fewer than four points (the row kernel):
+// a pixel holding more than half the samples a wavefront handles on average
+// over the launch would be a long tail, so pixels above max(KDE_PART, that
+// half) are split into parts of that many samples (a multiple of 16).  0: no
+// pixel is split.
 int64_t kde_part_size(const dsl_handle* h, int B) {
+  if (B >= 4) return 0;   // batches take the tile kernel, which walks whole pixels largest first
   const double per_wave = (double)h->n_samp * B / (4.0 * 16 * h->n_cu);
   int64_t P = std::max<int64_t>(KDE_PART, (int64_t)std::ceil(0.5 * per_wave));
   P = (P + 15) / 16 * 16;
@@ -513,8 +546,7 @@ bool merge_events(const dsl_handle* h) {
   return h->numerator == 0 && h->n_events > 0 && h->inj_slot0 >= 16 * h->n_events;
 }
 
-// Device workspace of one call: the handle's buffers, or (for the
-// allocation-free entry point) ranges of the per-device static scratch.
+// Device workspace of one call: the handle's buffers.
 struct Ws {
   void* lamc = nullptr;
   void* cos_tab = nullptr;
@@ -522,6 +554,7 @@ struct Ws {
   void* wg_tab = nullptr;
   void* valid = nullptr;
   void* gmap = nullptr;
+  void* cos64 = nullptr;   // FP64 cosmology records (FP32 handles)
   void* part = nullptr;
   void* cpart = nullptr;
   void* ev_rec = nullptr;
@@ -540,7 +573,7 @@ struct WsNeed {
 };
 
 struct WsNeeds {
-  WsNeed v[12];
+  WsNeed v[14];
   int n = 0;
   void add(DevBuf* b, void** d, size_t bytes, const char* what) { v[n++] = WsNeed{b, d, bytes, what}; }
   const WsNeed* begin() const { return v; }
@@ -561,6 +594,7 @@ WsNeeds workspace_needs(dsl_handle* h, int B, bool grad, Ws& ws) {
   n.add(&h->wg_tab, &ws.wg_tab, 6 * t1 * (NWG + 1) * Bz, "wg");
   n.add(&h->valid, &ws.valid, sizeof(int) * Bz, "valid");
   n.add(&h->gmap, &ws.gmap, sizeof(double) * N_GMAP * Bz, "gmap");
+  if (h->fp32) n.add(&h->cos64, &ws.cos64, sizeof(double) * COS64_N * Bz, "FP64 cosmology records");
   n.add(&h->part, &ws.part, sizeof(double) * nf * Bz * (size_t)std::max(h->n_items, 1), "partials");
   n.add(&h->cpart, &ws.cpart, sizeof(double) * NF_CSLICE * Bz * (size_t)combine_slices(h, B), "combine slices");
   if (merge_events(h)) n.add(&h->ev_rec, &ws.ev_rec, sizeof(double) * nf * Bz * (size_t)h->n_events, "event records");
@@ -607,17 +641,18 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
   const int setup_threads = 2 * B < h->n_cu ? 1024 : 256;
   HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, ws.lamc, ws.cos_tab, ws.win_tab,
                       grad ? ws.wg_tab : nullptr, (int*)ws.valid, grad ? (double*)ws.gmap : nullptr,
-                      setup_threads, st));
+                      (double*)ws.cos64, setup_threads, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
   SweepArgs a;
   a.samp = h->samp.p;
   a.inj = h->inj.p;
   a.pix_off = h->pix_off.as<int64_t>();
   a.pix_row = h->pix_row.as<int32_t>();
-  a.los = h->los.as<float>();
-  a.sky = h->sky.as<float>();
+  a.los = h->los.p;
+  a.sky = h->sky.p;
   a.n_z = h->n_z;
   a.z_max = h->z_max;
+  a.cos64 = (const double*)ws.cos64;
   a.items = h->items.as<WorkItem>();
   a.order = h->order.as<int32_t>();
   a.n_items = h->n_items;
@@ -652,10 +687,11 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
     k.pix_off = h->pix_off.as<int64_t>();
     k.pix_row = h->pix_row.as<int32_t>();
     k.perm = h->perm.as<int32_t>();
-    k.los = h->los.as<float>();
+    k.los = h->los.p;
     k.n_z = h->n_z;
     k.z_max = h->z_max;
     k.n_pix = h->n_pix;
+    k.order = h->kde_order.as<int32_t>();
     const bool split = kde_part_size(h, B) != 0;   // part list built for this B before the launch
     k.parts = split ? h->kde_parts.as<KdePart>() : nullptr;
     k.n_parts = split ? h->n_kde_parts : h->n_pix;
@@ -730,6 +766,7 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   // captured graphs hold workspace addresses: drop them all when any buffer moved
   const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
+                                        h->cos64.p,
                                         h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
                                         h->ev_rec.p,  h->kde_parts.p, h->ev_part_off.p};
   if (sig != h->ws_sig) {   // (a buffer that moved waited for the previous call first)
@@ -916,8 +953,8 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   }
   if ((rc = upload(h->pix_off, d->pix_samp_off, sizeof(int64_t) * (d->n_pix + 1)))) return rc;
   if ((rc = upload(h->pix_row, d->pix_los_row, sizeof(int32_t) * std::max<int64_t>(d->n_pix, 1)))) return rc;
-  if ((rc = upload(h->los, d->los, sizeof(float) * d->n_los_rows * (size_t)d->n_z))) return rc;
-  if ((rc = upload(h->sky, d->sky_z, sizeof(float) * d->n_z))) return rc;
+  if ((rc = upload_table(h.get(), h->los, d->los, d->los_f64, d->n_los_rows * (int64_t)d->n_z))) return rc;
+  if ((rc = upload_table(h.get(), h->sky, d->sky_z, d->sky_z_f64, d->n_z))) return rc;
   if ((rc = upload(h->ln_ns, ln_ns.data(), sizeof(double) * ln_ns.size()))) return rc;
   for (int64_t j = 0; j < d->n_pix; ++j) h->max_pix_samples = std::max(h->max_pix_samples, h->pso[j + 1] - h->pso[j]);
   if ((rc = upload(h->ev_pix_off, d->event_pix_off, sizeof(int64_t) * (d->n_events + 1)))) return rc;
@@ -933,6 +970,14 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
       std::sort(q, q + n, [x](int32_t u, int32_t v) { return x[u] < x[v] || (x[u] == x[v] && u < v); });
     }
     if ((rc = upload(h->perm, perm.data(), sizeof(int32_t) * d->n_samp))) return rc;
+    // pixels by decreasing sample count (ties by index): the batched KDE kernel's
+    // task order, so the largest pixels start first
+    std::vector<int32_t> ord(std::max<int64_t>(d->n_pix, 1));
+    for (int64_t j = 0; j < d->n_pix; ++j) ord[j] = (int32_t)j;
+    std::stable_sort(ord.begin(), ord.begin() + d->n_pix, [&](int32_t u, int32_t v) {
+      return h->pso[u + 1] - h->pso[u] > h->pso[v + 1] - h->pso[v];
+    });
+    if ((rc = upload(h->kde_order, ord.data(), sizeof(int32_t) * ord.size()))) return rc;
   }
   if ((rc = pack_samples(h.get(), h->samp, d->m1d, d->m2d, d->dl, d->ln_pi, d->n_samp))) return rc;
   if ((rc = pack_samples(h.get(), h->inj, d->inj_m1d, d->inj_m2d, d->inj_dl, d->inj_ln_pdraw, d->n_inj))) return rc;
@@ -1042,10 +1087,17 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
     else HIPCHK(hipEventElapsedTime(&ms, h->ev[4], h->ev[2]));
     *v = ms;
   }
+  else if (k == "work_list_bytes") *v = (double)(h->items.n + h->order.n + h->ev_item_off.n + h->splits.n);
   else if (k == "device_bytes") {
-    *v = (double)(h->samp.n + h->inj.n + h->pix_off.n + h->pix_row.n + h->los.n + h->sky.n + h->part.n +
-                  h->items.n + h->cos_tab.n + h->win_tab.n + h->wg_tab.n + h->perm.n + h->ev_part_off.n + h->kde_parts.n + h->ev_pix_off.n +
-                  h->kde_out.n + h->kde_ev.n + h->ev_rec.n + h->cpart.n);
+    const DevBuf* bufs[] = {&h->samp,      &h->inj,      &h->pix_off,    &h->pix_row,   &h->los,   &h->sky,
+                            &h->ln_ns,     &h->kde_parts, &h->ev_part_off, &h->ev_pix_off, &h->perm, &h->kde_order,
+                            &h->items,
+                            &h->order,     &h->ev_item_off, &h->splits,  &h->lamc,      &h->cos_tab, &h->win_tab,
+                            &h->wg_tab,    &h->valid,    &h->part,       &h->gmap,      &h->cos64, &h->kde_out, &h->kde_ev,
+                            &h->kde_evals, &h->cpart,    &h->ev_rec};
+    double sum = 0;
+    for (const DevBuf* b : bufs) sum += (double)b->n;
+    *v = sum;
   } else return fail(DSL_EINVAL, "unknown info key '" + k + "'");
   return DSL_OK;
 }

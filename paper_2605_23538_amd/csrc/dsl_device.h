@@ -41,15 +41,6 @@ __device__ __forceinline__ T hermite(T t, T y0, T d0, T y1, T d1) {
   const T h10 = h11 - t2 + t;
   return y0 + h01 * (y1 - y0) + h10 * d0 + h11 * d1;
 }
-template <typename T>
-__device__ __forceinline__ T hermite_dt(T t, T y0, T d0, T y1, T d1) {
-  const T t2 = t * t;
-  const T dh01 = (T)6 * (t - t2);
-  const T dh11 = (T)3 * t2 - (T)2 * t;
-  const T dh10 = dh11 - (T)2 * t + (T)1;
-  return dh01 * (y1 - y0) + dh10 * d0 + dh11 * d1;
-}
-
 // phi(x) = (e^x - 1)/x for |x| < 1/2 (Taylor, relative error < 1e-9) and its derivative.
 template <typename T>
 __device__ __forceinline__ T phi_series(T x) {
@@ -97,21 +88,62 @@ __device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv,
   return u * hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
 }
 
+// FP64 redshift of u = d_L H0 / c from a nearby z0 (a call: the rare path
+// stays out of the sweep loop's registers): two Newton steps on
+// (1+z) I(z) = u, I from the point's FP64 record {Omega_m, panel width,
+// I(panel starts)...} plus 8-point Gauss-Legendre over the partial panel.
+__device__ __noinline__ double z_fp64(double u, double z0, const double* __restrict__ rec) {
+  constexpr double X[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290, -0.1834346424956498,
+                           0.1834346424956498,  0.5255324099163290,  0.7966664774136267,  0.9602898564975363};
+  constexpr double W[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873, 0.3626837833783620,
+                           0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+  const double Om = rec[0], hz = rec[1];
+  const double* It = rec + 3;
+  auto E = [&](double x) { const double a = 1.0 + x; return ::sqrt(Om * a * a * a + (1.0 - Om)); };
+  double z = z0;
+  for (int it = 0; it < 2; ++it) {
+    int k = (int)(z / hz);
+    k = k < 0 ? 0 : (k > KZ_I - 1 ? KZ_I - 1 : k);
+    const double a = k * hz, h = z - a;
+    double sacc = 0.0;
+    for (int q = 0; q < 8; ++q) sacc += W[q] / E(a + 0.5 * h * (X[q] + 1.0));
+    const double I = It[k] + 0.5 * h * sacc;
+    z -= ((1.0 + z) * I - u) / (I + (1.0 + z) / E(z));
+  }
+  return z;
+}
+
+// Both nodes of a redshift-prior cell: one 8-byte load for float tables (the
+// table's base stays scalar, the offset a 32-bit lane value), two for double.
+__device__ __forceinline__ void los_pair(const float* __restrict__ t, uint32_t k, float& l0, float& l1) {
+  const float2 lp = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(t) + k * 4u);
+  l0 = lp.x;
+  l1 = lp.y;
+}
+__device__ __forceinline__ void los_pair(const double* __restrict__ t, uint32_t k, double& l0, double& l1) {
+  l0 = t[k];
+  l1 = t[k + 1];
+}
+
 // Evaluates w = 2^n * lin for one sample and one Lambda; lin = 0 outside the
 // support.  With GRAD, g[p] = d ln w / d Lambda_p (natural log; not set where
 // lin = 0).  With KW (the
 // KDE numerator's weights) the redshift prior and the rate are left out of w
 // and *z_out receives the sample's redshift, or -1 beyond z_max.  SPEC selects
 // the comoving-volume redshift prior (spectral sirens) instead of the table.
+// With cos64 (FP32 adjoint sweep, table prior) a sample within FP32 reach of
+// a table node takes its cell from its FP64 redshift, so the cell -- and with
+// it the slope that the gradient uses -- is the one an FP64 evaluation picks.
 template <typename T, int GL, bool GRAD, bool KW = false, bool SPEC = false>
 __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
-                                            const float* __restrict__ los, int n_z, T inv_dz, int& n_out,
-                                            T& lin_out, T* g, T* z_out = nullptr) {
+                                            const T* __restrict__ los, int n_z, T inv_dz, int& n_out,
+                                            T& lin_out, T* g, T* z_out = nullptr,
+                                            const double* __restrict__ cos64 = nullptr, double dz64 = 0.0) {
   static_assert(!(GRAD && KW), "the KDE weights have no adjoint");
   using M = Mth<T>;
   constexpr int NW = Tab<T>::NW;
   const T ln2 = (T)LN2;
-  const T u = sp.dlc * c.H0;
+  const T u = fma(sp.dlc, c.H0, sp.dlc * c.H0_lo);   // H0 carried to twice FP32 precision
   bool ok = u <= c.u_max;
   const T z = z_of_u<T, GL>(u, c, tv, lam);
   if constexpr (KW) *z_out = ok ? z : (T)-1;
@@ -136,11 +168,16 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     const T xz = z * inv_dz;
     int kz = (int)xz;
     kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
+    if constexpr (sizeof(T) == 4 && GRAD) {   // (ln L is continuous across nodes; its slope is not)
+      const T fr = xz - (T)(int)xz;
+      if (cos64 && ok && (fr < (T)NODE_TAU * xz || (T)1 - fr < (T)NODE_TAU * xz)) {
+        const double u64 = ((double)sp.dlc + (double)sp.dlc_lo) * ((double)c.H0 + (double)c.H0_lo);
+        const int k64 = (int)floor(z_fp64(u64, (double)z, cos64) / dz64);
+        kz = k64 < 0 ? 0 : (k64 > n_z - 2 ? n_z - 2 : k64);
+      }
+    }
     const T fz = xz - (T)kz;
-    // both nodes in one load: the table's base stays scalar, the offset a 32-bit lane value
-    const float2 lp = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(los) + (uint32_t)kz * 4u);
-    l0 = (T)lp.x;
-    l1 = (T)lp.y;
+    los_pair(los, (uint32_t)kz, l0, l1);
     losv = l0 + fz * (l1 - l0);
   } else {
     losv = I * I * rE;
@@ -152,12 +189,13 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T Xf = (T)1 + aX;
   // Mixture (in log2): power law, low peak, high peak.
   const T tP = c.cP - c.alpha * lm1;
-  const T dLo = m1 - c.muL, dHi = m1 - c.muH;
+  const T dLo = (m1 - c.muL) - c.muL_lo, dHi = (m1 - c.muH) - c.muH_lo;
   const T tL = c.cL + c.kL * dLo * dLo;
   const T tH = c.cH + c.kH * dHi * dHi;
   const T mx = fmax(tP, fmax(tL, tH));
   // Conditional-mass normaliser over m1^(beta+1): rho (window table or closed form).
-  const T t1 = (m1 - c.mmin) * c.inv_dm;
+  const T mp1 = (m1 - c.mmin) - c.mmin_lo;   // m1 - m_min
+  const T t1 = mp1 * c.inv_dm;
   // a window of zero width is a step at m_min: rho then has the closed form above M = m_min
   const bool inwin = c.dm > (T)0 && t1 < (T)1;
   const T xw = t1 * (T)NW;
@@ -167,7 +205,14 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const auto Wa = tv.win[kw * GL + lam];
   const auto Wb = tv.win[(kw + 1) * GL + lam];
   const T rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
-  const T ell2 = fmax(lm1 - c.lM, (T)0);       // log2(m1 / M) above the window
+  // ell2 = log2(m1 / M) above the window.  Near the window's edge, where rho is
+  // about Z_w/M^s + ln(m1/M), it comes from m1 - M (carried with m_min's
+  // rounding residual) as 2 atanh(x / (2 + x)), x = m1/M - 1 (series to x^9:
+  // relative error < 1e-9 for x < 1/4); further out as log2(m1) - log2(M).
+  const T xM = fmax(mp1 - c.dm, (T)0) * c.inv_M;
+  const T wM = xM * M::rcp((T)2 + xM), wM2 = wM * wM;
+  const T atn = wM * ((T)1 + wM2 * ((T)(1.0 / 3) + wM2 * ((T)(1.0 / 5) + wM2 * ((T)(1.0 / 7) + wM2 * (T)(1.0 / 9)))));
+  const T ell2 = xM < (T)0.25 ? (T)(2.0 * LOG2E) * atn : fmax(lm1 - c.lM, (T)0);
   const T sl = c.s * ell2;
   const T Em = M::exp2(-sl);                  // (M/m1)^s
   const T xs = -sl * ln2;
@@ -177,7 +222,7 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T rho = inwin ? rho_w : rho_a;
   ok = ok && (rho > (T)0);
   // Smoothing of m2: S = 1/(1 + 2^Y) in window.
-  const T mp2 = m2 - c.mmin;
+  const T mp2 = (m2 - c.mmin) - c.mmin_lo;
   const bool w2 = mp2 < c.dm;
   const T mq = mp2 * (mp2 - c.dm);
   const T rq = M::rcp(mq);
@@ -215,13 +260,19 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     const T lratio = (L - c.Lp) * ln2;        // ln((1+z)/(1+z_p))
     // m1 d ln Mix / d m1
     const T m1dmix = -c.alpha * fP - m1 * (dLo * c.isL2 * fL + dHi * c.isH2 * fH);
-    // m1 d ln rho / d m1
-    T m1dlnrho;
+    // In the window, S'/S at m1 (the local part of the derivatives of rho):
+    // d ln S/dm1 = (1 - S(m1)) dm (1/x^2 + 1/(x - dm)^2), x = m1 - m_min
+    T dlnS1 = 0;
     if (inwin) {
-      m1dlnrho = m1 * hermite_dt<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y) * (T)NW * c.inv_dm * rrho;
-    } else {
-      m1dlnrho = Em * ((T)1 - c.s * c.zw) * rrho;
+      const T rq1 = M::rcp(mp1 * (mp1 - c.dm));
+      const T Y1 = c.dm * ((T)2 * mp1 - c.dm) * rq1 * (T)LOG2E;   // S(m1) = 1/(1 + 2^Y1)
+      const T a1 = M::exp2(-fabs(Y1));
+      const T omS1 = (Y1 > (T)0 ? (T)1 : a1) * M::rcp((T)1 + a1);
+      const T i1 = (mp1 - c.dm) * rq1, i2 = mp1 * rq1;   // 1/x, 1/(x - dm)
+      dlnS1 = omS1 * c.dm * (i1 * i1 + i2 * i2);
     }
+    // m1 d ln rho / d m1: rho = Z/(S m1^s) gives 1/rho - m1 S'/S - s in the window
+    const T m1dlnrho = inwin ? rrho - m1 * dlnS1 - c.s : Em * ((T)1 - c.s * c.zw) * rrho;
     // S(m2) derivatives: d ln S/dm2 = (1-S)(dm/m'^2 + dm/(m'-dm)^2)
     T dlnS2_dm = 0, dlnS2_ddm = 0;
     if (w2) {
@@ -265,9 +316,10 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
       const auto Ga = wg[0], Gb = wg[GL];
       const auto Ha = wg[QS], Hb = wg[QS + GL];
       const auto Ka = wg[2 * QS], Kb = wg[2 * QS + GL];
+      // window-integral parts from the tables, local parts S'/S at m1 per sample
       drho_b = hermite<T>(tg, Ga.x, Ga.y, Gb.x, Gb.y);
-      drho_mmin = hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
-      drho_dm = hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
+      drho_mmin = rho_w * dlnS1 - hermite<T>(tg, Ha.x, Ha.y, Hb.x, Hb.y);
+      drho_dm = rho_w * t1 * dlnS1 - hermite<T>(tg, Ka.x, Ka.y, Kb.x, Kb.y);
     } else {
       const T ell = ell2 * ln2;
       // ell^2 phi'(x), x = -s ell: series, or (x e^x - e^x + 1)/s^2 with e^x = Em
@@ -297,6 +349,20 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     g[13] = L;
     g[14] = sig * lratio;
     g[15] = sig;
+  }
+}
+
+// Sample record loads: with one sample per wavefront (NS == 1) the address is
+// uniform, so it goes through the scalar cache (constant address space).
+template <typename T, int NS>
+__device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_t i) {
+  if constexpr (NS == 1) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(i & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(i >> 32));
+    const int64_t u = ((int64_t)hi << 32) | (uint32_t)lo;
+    return p[u];
+  } else {
+    return p[i];
   }
 }
 

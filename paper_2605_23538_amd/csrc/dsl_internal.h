@@ -18,10 +18,21 @@ constexpr int NU_F32 = 64;
 constexpr int NW_F32 = 64;
 constexpr int NU_F64 = 1024;
 constexpr int NW_F64 = 256;
-// The adjoint's window-derivative tables use every second node (Hermite, with
-// tangents from 5-point differences on the full grid).
+// The adjoint's window tables (the window-integral parts of d rho/d(beta,
+// m_min, delta_m)) use every second node, Hermite with analytic tangents.
 constexpr int NWG_F32 = NW_F32 / 2;
 constexpr int NWG_F64 = NW_F64 / 2;
+
+// Per-point FP64 cosmology record of the FP32 sweep: Omega_m, the panel width,
+// z_max and I(z) at the starts of KZ_I uniform panels over [0, z_max] and at
+// z_max (prefix sums of 8-point Gauss-Legendre), for the FP64 redshift of
+// samples near a redshift-table node.
+constexpr int KZ_I = 256;
+constexpr int COS64_N = 3 + KZ_I + 1;
+// A sample whose table coordinate z/dz lies within this relative distance of
+// a node takes its cell from its FP64 redshift (FP32 redshifts are within
+// 3.2e-7 of it).
+constexpr float NODE_TAU = 8e-7f;
 
 constexpr int R_SENTINEL = -(1 << 20);   // "no weight yet" binary exponent
 constexpr int RESCALE_MARGIN = 60;        // new max exponent that forces a rescale
@@ -38,6 +49,7 @@ struct LamC {
   T cP, cL, cH;    // log2 of mixture weight x component normalisation
   T muL, kL, muH, kH;   // peak centres, -log2(e) / (2 sigma^2)
   T s, inv_s, lM, zw;   // beta+1, 1/(beta+1), log2(m_min+delta_m), Z_w / M^s
+  T inv_M;              // 1/(m_min+delta_m)
   T gm3, gk, Lp;   // gamma - 3, gamma + kappa, log2(1 + z_p)
   // --- gradient constants (natural-log derivatives of the normalisations)
   T dbP_alpha, dbP_mmin, dbP_mmax;            // d ln b_P
@@ -52,6 +64,10 @@ struct LamC {
   T isL2, isL3, isH2, isH3;                   // sigma^-2, sigma^-3 of the peaks
   T aPg, aLg, aLl, aHl;                       // 1/(1-lg), 1/lg, 1/ll, 1/(1-ll) (0 at the edges)
   T inv_s2;                                   // 1/(beta+1)^2
+  // rounding residuals (x - (T)x) of the constants whose FP32 rounding would
+  // shift every sample alike: H0 (through u) and the mass locations m_min,
+  // mu_low, mu_high (through the differences m - x); 0 in FP64
+  T H0_lo, mmin_lo, muL_lo, muH_lo;
   int om_case;                                // 0 general, 1 Om ~ 0, 2 Om ~ 1
   int valid;
 };
@@ -85,7 +101,7 @@ struct Samp {
   T dlc;           // d_L / c  [Mpc s/km]
   T nlp;           // -ln(prior) / ln 2
   T lq;            // log2(m2d / m1d)
-  T inv_m1d;       // 1 / m1d
+  T dlc_lo;        // d_L / c - dlc (rounding residual; 0 in FP64)
 };
 
 // Fields of one partial result (per work item and Lambda).
@@ -97,10 +113,11 @@ struct SweepArgs {
   const void* inj;           // Samp<T>[n_inj]
   const int64_t* pix_off;    // [n_pix + 1]
   const int32_t* pix_row;    // [n_pix]
-  const float* los;          // [rows][n_z]
-  const float* sky;          // [n_z]
+  const void* los;           // [rows][n_z] of T
+  const void* sky;           // [n_z] of T
   int32_t n_z;
   double z_max;
+  const double* cos64;       // [B][COS64_N] FP64 cosmology records (FP32 sweep), or null
   const WorkItem* items;     // in slot order
   const int32_t* order;      // processing order of items
   int32_t n_items;
@@ -138,10 +155,11 @@ struct KdeArgs {
   const int64_t* pix_off;    // [n_pix + 1]
   const int32_t* pix_row;    // [n_pix]
   const int32_t* perm;       // [n_samp] per pixel: local indices in ascending d_L order
-  const float* los;          // [rows][n_z]
+  const void* los;           // [rows][n_z] of T
   int32_t n_z;
   double z_max;
   int64_t n_pix;
+  const int32_t* order;      // [n_pix] pixels by decreasing sample count (batched kernel), or null
   const KdePart* parts;      // [n_parts], pixel-major; null: one part per pixel (n_parts = n_pix)
   int64_t n_parts;
   const void* lamc;          // LamC<T>[B]

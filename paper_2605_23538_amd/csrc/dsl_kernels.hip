@@ -74,7 +74,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
                                                     typename V2<T>::t* __restrict__ cos_tab,
                                                     typename V2<T>::t* __restrict__ win_tab,
                                                     typename V2<T>::t* __restrict__ win_grad_tab,
-                                                    int* __restrict__ valid_out, double* __restrict__ gmap) {
+                                                    int* __restrict__ valid_out, double* __restrict__ gmap,
+                                                    double* __restrict__ cos64) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW, NWG = Tab<T>::NWG;
   const int b = blockIdx.x;
@@ -90,7 +91,6 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
   __shared__ double zw_s[4];
   __shared__ double cum[NW + 1];
   __shared__ double cumg[3][NW + 1];
-  __shared__ double gfine[3][NW + 1];
   const int tid = threadIdx.x;
   const double M = mmin + dm;
   const double s = beta + 1.0;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
   LamC<T>& c = lamc[b];
   if (part == 0) {
     // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
-    constexpr int KZ = 256;
+    constexpr int KZ = KZ_I;
     __shared__ double Itab[KZ + 1];
     const double hz = z_max / KZ;
     for (int k = tid; k < KZ; k += blockDim.x) {
@@ -118,6 +118,15 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
       for (int k = 1; k <= KZ; ++k) Itab[k] += Itab[k - 1];
     }
     __syncthreads();
+    if (cos64) {   // the FP64 record of the point (FP32 sweep: redshifts near table nodes)
+      double* rec = cos64 + (size_t)b * COS64_N;
+      for (int k = tid; k <= KZ; k += blockDim.x) rec[3 + k] = Itab[k];
+      if (tid == 0) {
+        rec[0] = Om;
+        rec[1] = hz;
+        rec[2] = z_max;
+      }
+    }
     // I(z) = Itab[k] + 8-point Gauss-Legendre over [z_k, z]
     auto I_at = [&](double z) {
       int k = (int)(z / hz);
@@ -168,6 +177,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
 
     if (tid == 0) {
       c.H0 = (T)H0;
+      c.H0_lo = (T)(H0 - (double)(T)H0);
       c.u_max = (T)umax;
       c.inv_hv = (T)(1.0 / hv);
       c.Om = (T)Om;
@@ -215,8 +225,10 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
     gpk[gl][4] = -pb / sg / dP;
   }
   // --- smoothing-window integrals on NW panels (Gauss-Legendre 8 x 2 per
-  // panel): integrals of m^beta S, and of m^beta d S/d(beta, m_min, dm) for the
-  // adjoint, one quarter panel (four nodes) per thread.
+  // panel), one quarter panel (four nodes) per thread: Z = int m^beta S and,
+  // for the adjoint, int m^beta ln(m) S, J = int m^beta S' and K = int m^beta
+  // tau S' (S' = dS/dm, tau = (m - m_min) / dm).  S(m) depends on m_min and dm
+  // only through tau, so dS/dm_min = -S' and dS/d(dm) = -tau S'.
   __shared__ double qsum[4][4 * NW];
   const bool win = ok && dm > 0;
   for (int i = tid; i < 4 * NW; i += blockDim.x) {
@@ -235,8 +247,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
         const double mb = exp(beta * lm);
         a0 += wq * mb * sd.S;
         a1 += wq * mb * lm * sd.S;
-        a2 += wq * mb * sd.S * (-sd.dlnS_dm);    // dS/dm_min = -dS/dm
-        a3 += wq * mb * sd.S * sd.dlnS_ddm;
+        a2 += wq * mb * sd.S * sd.dlnS_dm;
+        a3 += wq * mb * sd.S * sd.dlnS_dm * t;
       }
     }
     qsum[0][i] = a0;
@@ -261,48 +273,62 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
     // moves with m_min.  Divided by M^s = m_min^(beta+1), the one-sided limits
     // are d/d m_min -> -1/m_min and d/d delta_m -> -1/(2 m_min).
     const double zw0 = (ok && dm == 0.0) ? (tid == 2 ? -1.0 / mmin : (tid == 3 ? -0.5 / mmin : 0.0)) : 0.0;
-    zw_s[tid] = win ? run / exp(s * log(M)) : zw0;
+    // window integrals of m^beta dS/d(m_min) = -J and of m^beta dS/d(dm) = -K
+    const double sgn = tid >= 2 ? -1.0 : 1.0;
+    zw_s[tid] = win ? sgn * run / exp(s * log(M)) : zw0;
   }
   __syncthreads();
-  // rho(t) = Z / (S m^s) and its t-derivative; gradient tables d rho / d(beta, m_min, dm).
+  // rho(t) = Z / (S m^s) and its t-derivative (Hermite data), t = (m - m_min) / dm.
   for (int j = tid; j <= NW; j += blockDim.x) {
-    double rho = 0, drho = 0, g[3] = {0, 0, 0};
+    double rho = 0, drho = 0;
     if (win && j > 0) {
       const double t = (double)j / NW;
       const double m = mmin + dm * t;
       const SmoothD sd = smooth_d(m - mmin, dm);
       const double ms = exp(s * log(m));
       const double Sd = (j == NW) ? 1.0 : sd.S;
-      const double Z = cum[j];
-      rho = Z / (Sd * ms);
+      rho = cum[j] / (Sd * ms);
       const double dlnS = (j == NW) ? 0.0 : sd.dlnS_dm;
       drho = dm * (1.0 / m - rho * (dlnS + s / m));
-      // d rho / d beta = Z_beta/(S m^s) - rho ln m
-      g[0] = cumg[0][j] / (Sd * ms) - rho * log(m);
-      // d rho / d m_min at fixed m1 = [Z_mmin - Z d ln S/d m_min] / (S m^s), d ln S / d m_min = -dlnS_dm
-      g[1] = (cumg[1][j] + Z * dlnS) / (Sd * ms);
-      g[2] = (cumg[2][j] - Z * ((j == NW) ? 0.0 : sd.dlnS_ddm)) / (Sd * ms);
     }
     T2 e;
     e.x = (T)rho;
     e.y = (T)(drho / NW);
     win_tab[(size_t)b * (NW + 1) + j] = e;
-    for (int q = 0; q < 3; ++q) gfine[q][j] = g[q];
   }
-  __syncthreads();
-  // Hermite data of the derivative tables on every second node; tangents from
-  // 5-point differences of the full grid (one-sided at the ends).
+  // Adjoint tables on every second node: the window-integral parts of the
+  // derivatives of rho at fixed m1,
+  //   d rho/d beta  = D,                D = int m^beta ln(m/m1) S dm / (S m1^s),
+  //   d rho/d m_min = -J~ + rho S'/S,   J~ = J / (S m1^s),
+  //   d rho/d dm    = -K~ + rho t S'/S, K~ = K / (S m1^s),
+  // whose local parts (S'/S at m1) the sweep adds per sample.  Tangents are
+  // analytic: d/dt [I(t) / (S m1^s)] = dm (f(m1) / (S m1^s) - [I / (S m1^s)] (S'/S + s/m1))
+  // for an integral I of integrand f (for D also the -dm rho/m1 of ln(m/m1)).
   if (win_grad_tab) {
-    const double hf = 1.0 / NW;
     for (int i = tid; i < 3 * (NWG + 1); i += blockDim.x) {
-      const int q = i / (NWG + 1), jc = i % (NWG + 1), j = 2 * jc;
-      const double* f = gfine[q];
-      double d;
-      if (j == 0) d = (-25 * f[0] + 48 * f[1] - 36 * f[2] + 16 * f[3] - 3 * f[4]) / (12 * hf);
-      else if (j == NW) d = (25 * f[NW] - 48 * f[NW - 1] + 36 * f[NW - 2] - 16 * f[NW - 3] + 3 * f[NW - 4]) / (12 * hf);
-      else d = (f[j - 2] - 8 * f[j - 1] + 8 * f[j + 1] - f[j + 2]) / (12 * hf);
+      const int q = i / (NWG + 1), jc = i % (NWG + 1), j = (NW / NWG) * jc;
+      double v = 0.0, d = 0.0;
+      if (win && j > 0) {
+        const double t = (double)j / NW;
+        const double m = mmin + dm * t;
+        const SmoothD sd = smooth_d(m - mmin, dm);
+        const double den = ((j == NW) ? 1.0 : sd.S) * exp(s * log(m));
+        const double dl = (j == NW) ? 0.0 : sd.dlnS_dm;
+        const double g = dl + s / m;
+        if (q == 0) {
+          const double rho = cum[j] / den;
+          v = (cumg[0][j] - log(m) * cum[j]) / den;
+          d = -dm * (rho / m + v * g);
+        } else if (q == 1) {
+          v = cumg[1][j] / den;
+          d = dm * (dl / m - v * g);
+        } else {
+          v = cumg[2][j] / den;
+          d = dm * (t * dl / m - v * g);
+        }
+      }
       T2 e;
-      e.x = (T)f[j];
+      e.x = (T)v;
       e.y = (T)(d / NWG);
       win_grad_tab[((size_t)b * 3 + q) * (NWG + 1) + jc] = e;
     }
@@ -332,6 +358,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
     c.alpha = (T)alpha;
     c.beta = (T)beta;
     c.mmin = (T)mmin;
+    c.mmin_lo = (T)(mmin - (double)(T)mmin);
     c.mmax = (T)mmax;
     c.dm = (T)dm;
     c.inv_dm = dm > 0 ? (T)(1.0 / dm) : (T)0;
@@ -339,12 +366,15 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
     c.cL = (T)((lg * ll > 0 ? log(lg * ll) : -INFINITY) * l2 + lnbL * l2);
     c.cH = (T)((lg * (1 - ll) > 0 ? log(lg * (1 - ll)) : -INFINITY) * l2 + lnbH * l2);
     c.muL = (T)muL;
+    c.muL_lo = (T)(muL - (double)(T)muL);
     c.kL = (T)(-l2 / (2 * sL * sL));
     c.muH = (T)muH;
+    c.muH_lo = (T)(muH - (double)(T)muH);
     c.kH = (T)(-l2 / (2 * sH * sH));
     c.s = (T)s;
     c.inv_s = (T)(1.0 / s);
     c.lM = (T)log2(M);
+    c.inv_M = (T)(1.0 / M);
     c.zw = (T)zw_s[0];
     c.dbP_alpha = (T)dbPa;
     c.dbP_mmin = (T)dbPmin;
@@ -426,27 +456,13 @@ struct ItemAcc {
   }
 };
 
-// Sample record loads: with one sample per wavefront (NS == 1) the address is
-// uniform, so it goes through the scalar cache (constant address space).
-template <typename T, int NS>
-__device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_t i) {
-  if constexpr (NS == 1) {
-    const int lo = __builtin_amdgcn_readfirstlane((int)(i & 0xffffffff));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(i >> 32));
-    const int64_t u = ((int64_t)hi << 32) | (uint32_t)lo;
-    return p[u];
-  } else {
-    return p[i];
-  }
-}
-
 // One run of samples [s0, s1) accumulated into acc; the next record is
 // loaded while the current one is evaluated.
 template <typename T, int GL, bool GRAD, bool SPEC, typename AccT>
 __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
                                           bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
-                                          const float* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
-                                          T* g) {
+                                          const T* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
+                                          T* g, const double* __restrict__ cos64, double dz64) {
   constexpr int NS = 64 / GL;
   if (s1 <= s0) return;
   // indices are clamped into the run; with several samples per wavefront two
@@ -466,7 +482,7 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
     if (sb + sg < s1 && live) {
       int n;
       T lin;
-      eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g);
+      eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g, nullptr, cos64, dz64);
       acc.template add<T>(n, lin, g);
     }
   }
@@ -527,6 +543,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
   const Samp<T>* __restrict__ samp = reinterpret_cast<const Samp<T>*>(a.samp);
   const Samp<T>* __restrict__ inj = reinterpret_cast<const Samp<T>*>(a.inj);
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
+  const T* __restrict__ los = reinterpret_cast<const T*>(a.los);
+  const T* __restrict__ sky = reinterpret_cast<const T*>(a.sky);
+  // the point's FP64 record (FP32 table prior only): cells of samples near table nodes
+  const double* __restrict__ rec64 = (a.cos64 && !SPEC && active) ? a.cos64 + (size_t)b * COS64_N : nullptr;
+  const double dz64 = a.z_max / (double)(a.n_z - 1);
   T g[GRAD ? 16 : 1];
 
   for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
@@ -537,20 +558,20 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
     int npass = 0;
     if (w.event >= 0 && w.pix1 == w.pix0) {
       // part of a large pixel: ungated sums, gated after the sweep (gate_split_kernel)
-      const float* __restrict__ tab = SPEC ? nullptr : a.los + (size_t)a.pix_row[w.pix0] * a.n_z;
+      const T* __restrict__ tab = SPEC ? nullptr : los + (size_t)a.pix_row[w.pix0] * a.n_z;
       PixAcc<GRAD, T> pix;
       pix.zero();
-      sweep_run<T, GL, GRAD, SPEC>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
+      sweep_run<T, GL, GRAD, SPEC>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, rec64, dz64);
 #pragma unroll
       for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
       chunk.merge(pix);
     } else if (w.event >= 0) {
       for (int p = w.pix0; p < w.pix1; ++p) {
         const int64_t s0 = a.pix_off[p], s1 = a.pix_off[p + 1];
-        const float* __restrict__ tab = SPEC ? nullptr : a.los + (size_t)a.pix_row[p] * a.n_z;
+        const T* __restrict__ tab = SPEC ? nullptr : los + (size_t)a.pix_row[p] * a.n_z;
         PixAcc<GRAD, T> pix;
         pix.zero();
-        sweep_run<T, GL, GRAD, SPEC>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g);
+        sweep_run<T, GL, GRAD, SPEC>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, rec64, dz64);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         bool pass;
@@ -568,8 +589,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
         PixAcc<GRAD, T> pix;
         pix.zero();
         const int64_t v1 = v0 + VP < w.s1 ? v0 + VP : w.s1;
-        sweep_run<T, GL, GRAD, SPEC>(inj, v0, v1, sg, live, c, tv, lam, SPEC ? nullptr : a.sky, a.n_z, inv_dz,
-                               pix, g);
+        sweep_run<T, GL, GRAD, SPEC>(inj, v0, v1, sg, live, c, tv, lam, SPEC ? nullptr : sky, a.n_z, inv_dz,
+                               pix, g, rec64, dz64);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         chunk.merge(pix);
@@ -985,7 +1006,7 @@ __global__ void pack_kernel(const double* __restrict__ m1d, const double* __rest
   s.dlc = (T)(dl[i] / C_KMS);
   s.nlp = (T)(-lnp[i] * LOG2E);
   s.lq = (T)log2(bq / a);
-  s.inv_m1d = (T)(1.0 / a);
+  s.dlc_lo = (T)(dl[i] / C_KMS - (double)s.dlc);
   out[i] = s;
 }
 
@@ -1011,14 +1032,15 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 
 // threads: per workgroup, 256 ... SETUP_THREADS (the loops stride by the block size).
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, int threads, hipStream_t st) {
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* cos64, int threads,
+                        hipStream_t st) {
   if (threads < 256 || threads > SETUP_THREADS || threads % 64) return hipErrorInvalidValue;
   if (fp32)
     setup_kernel<float><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
-                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap);
+                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap, cos64);
   else
     setup_kernel<double><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
-                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap);
+                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap, cos64);
   return hipGetLastError();
 }
 

@@ -40,20 +40,26 @@ def test_header_layout_matches_binding():
     assert [f for f, _ in binding.CatalogDesc._fields_] == c_fields
 
 
-def _desc(binding, **over):
+def _desc(binding, tables="f32", **over):
+    """A valid one-event descriptor; `tables` gives the redshift-prior tables in
+    float32 ("f32"), float64 ("f64"), both or neither."""
     epo = np.array([0, 2], np.int64)
     pso = np.array([0, 1, 3], np.int64)
     row = np.array([0, 0], np.int32)
     los = np.ones(8, np.float32)
     sky = np.ones(8, np.float32)
     s = np.array([30.0, 35.0, 40.0])
-    keep = dict(epo=epo, pso=pso, row=row, los=los, sky=sky, m1=s, m2=s * 0.5, dl=s * 40, lp=s * 0,
+    keep = dict(epo=epo, pso=pso, row=row, los=los, sky=sky, los64=los.astype(np.float64),
+                sky64=sky.astype(np.float64), m1=s, m2=s * 0.5, dl=s * 40, lp=s * 0,
                 im1=s, im2=s * 0.5, idl=s * 40, ilp=s * 0)
     keep.update(over)
     p = lambda a: a.ctypes.data_as(C.c_void_p)
+    f32, f64 = tables in ("f32", "both"), tables in ("f64", "both")
     d = binding.CatalogDesc(n_events=1, event_pix_off=p(keep["epo"]), n_pix=2, pix_samp_off=p(keep["pso"]),
-                            pix_los_row=p(keep["row"]), n_los_rows=1, n_z=8, z_max=2.0, los=p(keep["los"]),
-                            sky_z=p(keep["sky"]), n_samp=3, m1d=p(keep["m1"]), m2d=p(keep["m2"]), dl=p(keep["dl"]),
+                            pix_los_row=p(keep["row"]), n_los_rows=1, n_z=8, z_max=2.0,
+                            los=p(keep["los"]) if f32 else None, sky_z=p(keep["sky"]) if f32 else None,
+                            los_f64=p(keep["los64"]) if f64 else None, sky_z_f64=p(keep["sky64"]) if f64 else None,
+                            n_samp=3, m1d=p(keep["m1"]), m2d=p(keep["m2"]), dl=p(keep["dl"]),
                             ln_pi=p(keep["lp"]), n_inj=3, inj_m1d=p(keep["im1"]), inj_m2d=p(keep["im2"]),
                             inj_dl=p(keep["idl"]), inj_ln_pdraw=p(keep["ilp"]), n_draw=10, precision=1)
     return d, keep
@@ -74,6 +80,22 @@ def test_create_rejects_malformed_catalogue(over, msg):
     h = C.c_void_p()
     rc = lib.dsl_create(C.byref(d), C.byref(h))
     assert rc == 1 and not h.value
+    assert msg in lib.dsl_last_error().decode()
+
+
+@pytest.mark.parametrize("tables,over,msg", [
+    ("both", {}, "exactly one"),
+    ("none", {}, "exactly one"),
+    ("f64", dict(los64=np.array([1, 1, 1, float("nan"), 1, 1, 1, 1])), "LOS"),
+    ("f64", dict(sky64=np.array([1, 1, 1, 1, 1, 1, 1, -1.0])), "sky_z"),
+])
+def test_create_checks_table_precision_choice(tables, over, msg):
+    """The tables come in float32 or in float64, never both; float64 tables are
+    checked like float32 ones."""
+    binding, lib = _lib()
+    d, keep = _desc(binding, tables=tables, **over)
+    h = C.c_void_p()
+    assert lib.dsl_create(C.byref(d), C.byref(h)) == 1 and not h.value
     assert msg in lib.dsl_last_error().decode()
 
 

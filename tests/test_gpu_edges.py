@@ -371,7 +371,9 @@ def test_delta_m_zero(mods, precision):
         ref = O.loglike(cat, lam[b], grad=True, margins=True)
         assert int(r["flags"][b]) == ref["flags"] == 0, (b, int(r["flags"][b]), ref["flags"])
         assert rel_close(float(r["logL"][b]), ref["logL"], tol), (b, float(r["logL"][b]), ref["logL"])
-        assert float(f["logL"][b]) == float(r["logL"][b])
+        # the adjoint takes the cell of samples next to a table node from their FP64
+        # redshift; the forward sweep's FP32 cell differs there only by rounding
+        assert rel_close(float(f["logL"][b]), float(r["logL"][b]), 1e-9)
         check_events(r["logL_event"][b].cpu().numpy(), r["neff_event"][b].cpu().numpy(), ref, tol)
         check_grad(r["grad"][b].cpu().numpy(), ref["grad"])
     lik.close()
@@ -427,7 +429,8 @@ def test_side_stream_alternating_batches(mods):
 def test_downsampling_device_bytes(mods):
     """A cap that binds (64 samples per pixel on a catalogue of about 125 per
     pixel): the handle holds (dropped samples) x (32-byte record + 4-byte order
-    index) fewer bytes, and the capped likelihood equals the oracle's on the
+    index) fewer bytes, apart from a shorter work list (its items cut the kept
+    samples into runs), and the capped likelihood equals the oracle's on the
     catalogue downsampled by the same rule."""
     torch, O, synth = mods["torch"], mods["O"], mods["synth"]
     cat = synth.make_catalog("c1")
@@ -438,7 +441,8 @@ def test_downsampling_device_bytes(mods):
     assert kept == ds.n_samp < cat.n_samp
     assert int(capped.info("n_samp_input")) == cat.n_samp
     drop = full.info("device_bytes") - capped.info("device_bytes")
-    assert drop == (cat.n_samp - kept) * (32 + 4), (drop, cat.n_samp, kept)
+    work = full.info("work_list_bytes") - capped.info("work_list_bytes")
+    assert drop - work == (cat.n_samp - kept) * (32 + 4), (drop, work, cat.n_samp, kept)
     log(f"  kept {kept} of {cat.n_samp} samples; device bytes {full.info('device_bytes'):.0f} -> "
         f"{capped.info('device_bytes'):.0f}")
     lam = synth.fiducial_lambda()

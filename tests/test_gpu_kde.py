@@ -112,12 +112,30 @@ def test_fewer_points_than_rows(env, precision, B, bandwidth):
         _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
 
 
+@pytest.mark.parametrize("B", [4, 20, 64])
+@pytest.mark.parametrize("bandwidth", BANDWIDTHS)
+def test_point_tiles_ragged(env, B, bandwidth):
+    """Batches take the tile kernel (4, 16 and 64 points per wavefront): pass A
+    with the points side by side, the passing points packed into rows for the
+    grid stage; ragged pixels (0 to 200 samples), every point against the
+    oracle, with and without the gate."""
+    synth = env["synth"]
+    log(f"[kde tiles B={B} {bandwidth}]")
+    cat = ragged_catalog(synth, RAGGED)
+    lam = synth.draw_lambdas(B, seed=61)
+    lam[0] = synth.fiducial_lambda()
+    for gate in (0, 2):
+        r = _run(env, cat, lam, kde_bandwidth=bandwidth, gate_mode=gate)
+        _check(env, cat, lam, r, TOL_LOGL_FP32, bandwidth=bandwidth, gate_mode=gate)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("B", [1, 5])
 @pytest.mark.parametrize("bandwidth", ["silverman", "biweight"])
 def test_split_pixels(env, precision, B, bandwidth):
-    """Pixels above 256 samples are split for the grid stage (each part keeps
-    the whole pixel's gate and bandwidth): sizes at and around the part size."""
+    """With fewer than four points, pixels above 256 samples are split for the
+    grid stage (each part keeps the whole pixel's gate and bandwidth): sizes at
+    and around the part size.  Batches (B = 5) walk whole pixels, largest first."""
     torch, synth = env["torch"], env["synth"]
     log(f"[kde split pixels B={B} {precision} {bandwidth}]")
     cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
@@ -129,8 +147,8 @@ def test_split_pixels(env, precision, B, bandwidth):
                                                  kde_bandwidth=bandwidth, gate_mode=gate)
         r = lik.loglike(torch.tensor(lam, device="cuda"), per_event=True)
         torch.cuda.synchronize()
-        # parts of 256: 1 + 2, 2 + 1 + 3, 4
-        assert lik.info("kde_units") == 13
+        # parts of 256: 1 + 2, 2 + 1 + 3, 4; whole pixels for batches
+        assert lik.info("kde_units") == (13 if B < 4 else 6)
         lik.close()
         _check(env, cat, lam, r, tol, bandwidth=bandwidth, gate_mode=gate)
 
@@ -254,9 +272,10 @@ def test_kde_work_counters(env):
 
 
 def test_part_list_rebuilds_with_graphs(env):
-    """One handle, graph replay on, batches that need different part sizes
-    (256 samples for one point, 320 for 4096 points): every call equals an
-    eager call of the same batch, bitwise."""
+    """One handle, graph replay on, batches that take different kernels (the
+    row kernel with parts of 256 samples for one point, the tile kernel over
+    whole pixels for 4096 points): every call equals an eager call of the same
+    batch, bitwise."""
     torch, synth, binding = env["torch"], env["synth"], env["binding"]
     cat = ragged_catalog(synth, [[256, 257], [512, 3, 513], [1000]], n_inj=500)
     lams = {B: torch.tensor(synth.draw_lambdas(B, seed=83), device="cuda") for B in (1, 4096)}

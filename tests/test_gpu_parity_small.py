@@ -51,6 +51,48 @@ def test_config1_single_lambda(env, precision):
     lik.close()
 
 
+def test_float64_tables(env):
+    """Redshift-prior tables given in float64 (Eq. 5): an FP64 handle keeps them
+    in float64 and matches the oracle on them; an FP32 handle rounds them.  The
+    tables are the float32 ones times (1 + 2^-26), which float32 cannot hold
+    (they round back to the float32 tables), so each event's ln L_i moves by
+    ln(1 + 2^-26) = 1.5e-8 only where the float64 values are used."""
+    import dataclasses
+    torch, O, cat = env["torch"], env["O"], env["cat"]
+    log("[c1 float64 tables]")
+    los64 = cat.los.astype(np.float64) * (1.0 + 2.0 ** -26)
+    sky64 = cat.sky_z.astype(np.float64) * (1.0 + 2.0 ** -26)
+    assert np.array_equal(los64.astype(np.float32), cat.los) and not np.array_equal(los64, cat.los)
+    c64 = dataclasses.replace(cat, los=los64, sky_z=sky64)
+    lam = _lam(env, 3, 21)
+    lt = torch.tensor(lam, device="cuda")
+    l64 = env["binding"].DarkSirenLikelihood(c64, precision="fp64")
+    r64 = l64.loglike_grad(lt, per_event=True)
+    l32a = env["binding"].DarkSirenLikelihood(c64, precision="fp32")
+    r32a = l32a.loglike(lt, per_event=True)
+    l32b = env["binding"].DarkSirenLikelihood(cat, precision="fp32")
+    r32b = l32b.loglike(lt, per_event=True)
+    torch.cuda.synchronize()
+    # the FP32 handle converts the float64 tables to the float32 ones
+    assert torch.equal(r32a["logL"], r32b["logL"]) and torch.equal(r32a["logL_event"], r32b["logL_event"])
+    for b in range(len(lam)):
+        ref = O.loglike(c64, lam[b], grad=True)
+        ref32 = O.loglike(cat, lam[b])
+        if ref["flags"]:
+            assert float(r64["logL"][b]) == -math.inf
+            continue
+        ev = r64["logL_event"][b].cpu().numpy()
+        for i in range(cat.n_events):
+            assert rel_close(float(ev[i]), ref["logL_event"][i], TOL_LOGL_FP64), (b, i)
+        # the float64 values were used: ln L_i differs from the float32 tables' by 1.5e-8
+        d = ev - ref32["logL_event"]
+        assert np.all(np.abs(d - np.log1p(2.0 ** -26)) < 3e-9), (b, d)
+        assert rel_close(float(r64["logL"][b]), ref["logL"], TOL_LOGL_FP64)
+        check_grad(r64["grad"][b].cpu().numpy(), ref["grad"])
+    for h in (l64, l32a, l32b):
+        h.close()
+
+
 @pytest.mark.parametrize("tile", [1, 4, 16, 64])
 def test_batched_tiles_match_oracle(env, tile):
     """Batched points with every Lambda tile shape (ragged last tile, B = 9)."""
