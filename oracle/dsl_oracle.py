@@ -402,8 +402,20 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
     rows = torch.from_numpy(prow)[torch.from_numpy(pix_of_samp)]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a[samp], dtype=np.float64))
     margins = [] if margin_out is not None else None
-    lw = log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), tables, rows, cat.z_max, L, margins,
-                     z_prior=opt.z_prior)
+    m1d, m2d, dl = t(cat.m1d), t(cat.m2d), t(cat.dl)
+    lw = log_weights(m1d, m2d, dl, t(cat.ln_pi), tables, rows, cat.z_max, L, margins, z_prior=opt.z_prior)
+    if margin_out is not None:
+        # each sample's ln w under a perturbation of its inputs at FP32 reach:
+        # eps_dl = 3.2e-7 of d_L (FP32 redshifts are within 3.2e-7 of the FP64
+        # ones), 6e-8 of each mass (FP32 rounding); first order in the inputs
+        with torch.enable_grad():
+            xs = [v.detach().clone().requires_grad_(True) for v in (m1d, m2d, dl)]
+            L0 = Lam(*[getattr(L, f).detach() for f in L.__dataclass_fields__])
+            lw2 = log_weights(*xs, t(cat.ln_pi), tables, rows, cat.z_max, L0, z_prior=opt.z_prior)
+            ok2 = torch.isfinite(lw2)
+            gr = torch.autograd.grad(torch.where(ok2, lw2, torch.zeros_like(lw2)).sum(), xs)
+        cond = (3.2e-7 * torch.abs(dl * gr[2]) + 6e-8 * (torch.abs(m1d * gr[0]) + torch.abs(m2d * gr[1]))).detach()
+        cond = torch.where(ok2, cond, torch.zeros_like(cond))
     seg = torch.from_numpy(pix_of_samp)
     n_p = len(pix)
     lS1 = segment_lse(lw, seg, n_p)
@@ -445,7 +457,11 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
             sm = margins[0] if margins else torch.zeros(0, dtype=DT)
             smp = torch.full((n_p,), math.inf, dtype=DT).scatter_reduce(0, seg, sm, "amin")
             ev_samp = torch.full((nE,), math.inf, dtype=DT).scatter_reduce(0, ev_seg, smp, "amin")
-            margin_out.append((ev_gate.numpy(), ev_samp.numpy(), pix, gm.numpy()))
+            # per event: the weight-averaged sensitivity over its passing pixels
+            wk = torch.exp(lw.detach() - lE1.detach()[ev_seg][seg])
+            use = passing[seg] & torch.isfinite(wk)
+            ev_cond = torch.zeros(nE, dtype=DT).index_add(0, ev_seg[seg], torch.where(use, wk * cond, torch.zeros_like(cond)))
+            margin_out.append((ev_gate.numpy(), ev_samp.numpy(), pix, gm.numpy(), ev_cond.numpy()))
     return lnL, neff_ev
 
 
@@ -474,7 +490,9 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     decisions taken in another precision, and pixel_gate_margin[n_pix], that
     distance for every pixel (inf for a pixel without weight).  gate_flip (pixel
     ids) inverts the gate decision of those pixels, so such a test can evaluate
-    the other outcome.
+    the other outcome.  event_fp32_cond[n_events] bounds, to first order, how
+    far ln L_i moves when every sample's d_L is perturbed by 3.2e-7 and its
+    masses by 6e-8 (relative): the reach of an FP32 evaluation of the inputs.
     """
     lam_np = np.asarray(lam, dtype=np.float64).reshape(16)
     nE = cat.n_events
@@ -494,6 +512,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     gate_m = np.empty(nE)
     samp_m = np.empty(nE)
     pix_m = np.full(cat.n_pix, math.inf) if margins else None
+    ev_cond = np.zeros(nE)
     for b0 in range(0, nE, event_block):
         ids = np.arange(b0, min(nE, b0 + event_block))
         mo = [] if margins else None
@@ -504,7 +523,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         lnL_ev[ids] = lnL_b.detach().numpy()
         neff_ev[ids] = neff_b.numpy()
         if margins:
-            gate_m[ids], samp_m[ids], pix_b, pm_b = mo[0]
+            gate_m[ids], samp_m[ids], pix_b, pm_b, ev_cond[ids] = mo[0]
             pix_m[pix_b] = pm_b
     # Selection term: alpha = (1/N_draw) sum_n w_n, merged over chunks.
     lc1, lc2, gc = [], [], []
@@ -546,6 +565,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         out["sample_margin"] = samp_m
         out["inj_margin"] = inj_margin
         out["pixel_gate_margin"] = pix_m
+        out["event_fp32_cond"] = ev_cond
     return out
 
 

@@ -84,8 +84,13 @@ def compare_with_golden(z, logL, grad, logL_event, neff_event, tol_grad=TOL_GRAD
     the gradient.  Events holding pixels near the N_eff threshold may have been
     decided the other way in the launch's precision: for those, the stored
     outcome combination whose ln L_i is nearest the launch's is taken, and its
-    ln L_i and gradient change enter the expected totals.  Returns the number
-    of events resolved that way and the number decided differently."""
+    ln L_i and gradient change enter the expected totals.  Each ln L_i is
+    held to 1e-6 plus its sensitivity to the inputs at FP32 reach
+    (event_fp32_cond: a few samples in a narrow smoothing window can carry an
+    event, and their FP32 redshifts and masses move their weights by ~1e-4);
+    ln L itself to 1e-6.  Returns the number of events resolved against
+    alternatives, the number decided differently and the worst gradient entry
+    in units of its bound."""
     exp_ev = np.array(z["logL_event"], np.float64)
     exp_grad = np.array(z["grad"], np.float64)
     alt_ev, alt_mask = z["alt_event"], z["alt_mask"]
@@ -111,8 +116,10 @@ def compare_with_golden(z, logL, grad, logL_event, neff_event, tol_grad=TOL_GRAD
     # margin used here (among 1e7 injections a few do: one injection moves
     # ln alpha by about 1e-7 of itself, far inside the bounds below)
     assert float(np.min(z["sample_margin"])) > SAMPLE_MARGIN
+    cond = np.asarray(z["event_fp32_cond"])
     for i in range(len(exp_ev)):
-        assert rel_close(float(logL_event[i]), float(exp_ev[i]), TOL_LOGL_FP32), (i, logL_event[i], exp_ev[i])
+        tol = TOL_LOGL_FP32 * max(1.0, abs(float(exp_ev[i]))) + cond[i]
+        assert abs(float(logL_event[i]) - float(exp_ev[i])) <= tol, (i, logL_event[i], exp_ev[i], cond[i])
         if not amb[i]:
             rn = float(z["neff_event"][i])
             assert abs(neff_event[i] - rn) <= 1e-5 * max(1.0, rn), (i, neff_event[i], rn)
