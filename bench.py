@@ -23,16 +23,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per sample-weight (one sample or injection, one Lambda), in
-# FP operations with FMA = 2 and each transcendental = 1: the adjoint sweep's
-# figure is measured on the built kernel (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,
-# TRANS}_F32 + 2 x FMA_F32, plus the F64 counts, per sample-weight: 300; a
-# count from the source gives 360 because the kernel shares subexpressions
-# between the weight and its derivatives); the forward figure is counted from
-# the source (distance inversion, frame change, Jacobian, prior, rate, mixture,
-# window, smoothing, exponent bookkeeping).
-FLOP_PER_WEIGHT_FWD = 175
-FLOP_PER_WEIGHT_GRAD = 300
-# KDE numerator: the weight without prior and rate (164, from the source).  Per
+# FP operations with FMA = 2 and each exp2/log2/rcp/rsqrt/sqrt = 1: the op graph
+# of Eq. 7's weight, its Eq. 8 sums and (adjoint) its 16 log-derivatives and
+# basis sums, every per-Lambda quantity hoisted, on the common path (inside the
+# support, masses above the smoothing window, table redshift prior); the kernels
+# execute more (rounding residuals, window branches, exponent bookkeeping), which
+# the hardware counters show and the roofline does not credit.
+FLOP_PER_WEIGHT_FWD = 97
+FLOP_PER_WEIGHT_GRAD = 210
+# KDE numerator: the weight and its sums without prior and rate (87) and the
+# redshift moments (3).  Per
 # (sample, grid node) kernel term on a uniform grid, with the Gaussian's node-to-
 # node ratio recurrence: a multiply and an add, plus per sample and run of 16
 # nodes the start term (difference, square, exp2, weight) and the ratio (a
@@ -42,7 +42,7 @@ FLOP_PER_WEIGHT_GRAD = 300
 # two exponents, two exp2, sum, reciprocal: 9), products (2), the recurrence's
 # node factor 2^(-(i S)^2) (itself by a ratio recurrence: 3), the node's
 # dot-product term (2).
-FLOP_PER_KDE_WEIGHT = 164
+FLOP_PER_KDE_WEIGHT = 90
 FLOP_PER_KDE_NODE = 2.27
 FLOP_PER_KDE_GRID_NODE = 24
 PEAK_FP32_VECTOR_TFLOPS = 157.3        # MI355X published FP32 vector (packed) peak
@@ -86,6 +86,8 @@ def parse():
     p.add_argument("--kde-steps", type=int, default=3,
                    help="after the main timing on c4, time this many steps of the same points with the KDE "
                         "numerator on the same handle (0: skip); reported under 'kde_numerator'")
+    p.add_argument("--max-samples-per-pixel", type=int, default=0,
+                   help="keep at most this many posterior samples per pixel (seeded choice; 0: all)")
     p.add_argument("--copy-calib", type=int, default=0,
                    help="after the timed steps, run one elementwise copy of this many MiB (calibrates "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -175,7 +177,9 @@ def main():
           file=sys.stderr, flush=True)
     t0 = time.time()
     lik = binding.DarkSirenLikelihood(cat, precision=precision, numerator=args.numerator,
-                                      kde_bandwidth=args.kde_bandwidth)
+                                      kde_bandwidth=args.kde_bandwidth,
+                                      max_samples_per_pixel=args.max_samples_per_pixel)
+    n_samp = int(lik.info("n_samp"))   # posterior samples kept (all of them without a cap)
     print(f"# uploaded in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     lam_np = synth.lambdas_for(args.config, B)
     lam = torch.tensor(lam_np, device="cuda:0")
@@ -236,7 +240,7 @@ def main():
             pix_ms.append(lik.info("ms_pixels"))
     torch.cuda.synchronize()
     lik.set_option("timing", 0)
-    n_w = cat.n_samp + cat.n_inj
+    n_w = n_samp + cat.n_inj
     flags_h = flags.cpu().numpy()
     finite = int(np.isfinite(logL.cpu().numpy()).sum())
 
@@ -249,7 +253,7 @@ def main():
         kde_evals = lik.info("kde_evals")
         kde_nodes = lik.info("kde_nodes")
         kde_avg = float(np.mean(pix_ms))
-        flops = (FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kde_evals
+        flops = (FLOP_PER_KDE_WEIGHT * n_samp * B + FLOP_PER_KDE_NODE * kde_evals
                  + FLOP_PER_KDE_GRID_NODE * kde_nodes)
         achieved = flops / (kde_avg * 1e-3) / 1e12
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
@@ -262,7 +266,7 @@ def main():
     # the algorithmic bytes (every sample and injection record once, every LOS
     # table once, the per-item partial sums written and read back once)
     if kde:   # the KDE stage: sample records, tables, one {R, T, S1, S2} record per (pixel, point)
-        alg_bytes = 32 * cat.n_samp + cat.los.nbytes + 2 * 32 * B * cat.n_pix
+        alg_bytes = 32 * n_samp + cat.los.nbytes + 2 * 32 * B * cat.n_pix
     else:
         alg_bytes = 32 * n_w + cat.los.nbytes + 2 * (20 if grad else 4) * 8 * B * int(lik.info("n_items"))
     kt = (kde_avg if kde else sweep_avg) * 1e-3
@@ -280,7 +284,7 @@ def main():
                 **({"flop_per_kde_weight": FLOP_PER_KDE_WEIGHT, "flop_per_kde_node": FLOP_PER_KDE_NODE,
                     "flop_per_kde_grid_node": FLOP_PER_KDE_GRID_NODE,
                     "kde_node_evals_per_launch": kde_evals, "kde_grid_nodes_per_launch": kde_nodes,
-                    "kde_weights_per_launch": cat.n_samp * B}
+                    "kde_weights_per_launch": n_samp * B}
                    if kde else {"flop_per_weight": F, "weights_per_launch": n_w * B}),
                 "chunk": int(lik.info("chunk")), "items": int(lik.info("n_items"))}
 
@@ -353,7 +357,7 @@ def main():
         kev = lik.info("kde_evals")
         knodes = lik.info("kde_nodes")
         kavg = float(np.mean(kms))
-        kfl = FLOP_PER_KDE_WEIGHT * cat.n_samp * B + FLOP_PER_KDE_NODE * kev + FLOP_PER_KDE_GRID_NODE * knodes
+        kfl = FLOP_PER_KDE_WEIGHT * n_samp * B + FLOP_PER_KDE_NODE * kev + FLOP_PER_KDE_GRID_NODE * knodes
         kach = kfl / (kavg * 1e-3) / 1e12
         kde_side = {"metric": "Lambda-evaluations/sec (log L, KDE numerator (%s), %d-node grid)"
                               % (args.kde_bandwidth, int(lik.info("kde_grid"))),
@@ -370,7 +374,7 @@ def main():
         lik.set_option("numerator", 0)
 
     cpu = None
-    if not args.no_cpu_baseline and args.config in ("c4", "c2"):
+    if not args.no_cpu_baseline and args.config in ("c4", "c2") and not args.max_samples_per_pixel:
         cpu = cpu_baseline(cat, lam_np[0], grad, args.kde_bandwidth if kde else None)
 
     what = "log L, KDE numerator (%s)" % args.kde_bandwidth if kde else "log L + grad" if grad else "log L"
@@ -382,14 +386,16 @@ def main():
         "ms_per_step_hip_events": round(ms_per_step_events, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d events, %d samples, %d pixels x %d-node LOS tables (%.2f GB), %d injections, "
+        "config": {"workload": "%s: %d events, %d samples%s, %d pixels x %d-node LOS tables (%.2f GB), %d injections, "
                                "%d Lambda per launch, %s"
                                % ({"c4": "O5-like batched (c4)"}.get(args.config, args.config), cat.n_events,
-                                  cat.n_samp, cat.n_pix, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B,
+                                  n_samp, (" (at most %d per pixel, of %d)" % (args.max_samples_per_pixel, cat.n_samp)
+                                           if args.max_samples_per_pixel else ""), cat.n_pix, cat.n_z, cat.los.nbytes / 1e9, cat.n_inj, B,
                                   "ln L + d ln L/d Lambda (16 entries)" if grad
                                   else "ln L with the KDE numerator (%s, %d-node grid)"
                                   % (args.kde_bandwidth, int(lik.info("kde_grid"))) if kde else "ln L"),
-                   "B": B, "precision": "FP32 weights, FP64 sums" if precision == "fp32" else "FP64"},
+                   "B": B, "precision": "FP32 weights, FP64 sums" if precision == "fp32" else "FP64",
+                   **({"max_samples_per_pixel": args.max_samples_per_pixel} if args.max_samples_per_pixel else {})},
         "gsample_weights_per_s": round(n_w * B * args.steps / wall / 1e9, 3),
         "kernel_timing": "HIP events around each kernel on the launch stream, a second pass of K steps",
         "kernel_ms": {"setup": round(float(np.mean(setup_ms)), 4), "sweep": round(sweep_avg, 4),

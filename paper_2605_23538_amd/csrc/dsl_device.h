@@ -88,31 +88,6 @@ __device__ __forceinline__ T z_of_u(T u, const LamC<T>& c, const TabView<T>& tv,
   return u * hermite<T>(tv_, A.x, A.y, Bn.x, Bn.y);
 }
 
-// FP64 redshift of u = d_L H0 / c from a nearby z0 (a call: the rare path
-// stays out of the sweep loop's registers): two Newton steps on
-// (1+z) I(z) = u, I from the point's FP64 record {Omega_m, panel width,
-// I(panel starts)...} plus 8-point Gauss-Legendre over the partial panel.
-__device__ __noinline__ double z_fp64(double u, double z0, const double* __restrict__ rec) {
-  constexpr double X[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290, -0.1834346424956498,
-                           0.1834346424956498,  0.5255324099163290,  0.7966664774136267,  0.9602898564975363};
-  constexpr double W[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873, 0.3626837833783620,
-                           0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
-  const double Om = rec[0], hz = rec[1];
-  const double* It = rec + 3;
-  auto E = [&](double x) { const double a = 1.0 + x; return ::sqrt(Om * a * a * a + (1.0 - Om)); };
-  double z = z0;
-  for (int it = 0; it < 2; ++it) {
-    int k = (int)(z / hz);
-    k = k < 0 ? 0 : (k > KZ_I - 1 ? KZ_I - 1 : k);
-    const double a = k * hz, h = z - a;
-    double sacc = 0.0;
-    for (int q = 0; q < 8; ++q) sacc += W[q] / E(a + 0.5 * h * (X[q] + 1.0));
-    const double I = It[k] + 0.5 * h * sacc;
-    z -= ((1.0 + z) * I - u) / (I + (1.0 + z) / E(z));
-  }
-  return z;
-}
-
 // Both nodes of a redshift-prior cell: one 8-byte load for float tables (the
 // table's base stays scalar, the offset a 32-bit lane value), two for double.
 __device__ __forceinline__ void los_pair(const float* __restrict__ t, uint32_t k, float& l0, float& l1) {
@@ -131,14 +106,16 @@ __device__ __forceinline__ void los_pair(const double* __restrict__ t, uint32_t 
 // KDE numerator's weights) the redshift prior and the rate are left out of w
 // and *z_out receives the sample's redshift, or -1 beyond z_max.  SPEC selects
 // the comoving-volume redshift prior (spectral sirens) instead of the table.
-// With cos64 (FP32 adjoint sweep, table prior) a sample within FP32 reach of
-// a table node takes its cell from its FP64 redshift, so the cell -- and with
-// it the slope that the gradient uses -- is the one an FP64 evaluation picks.
+// With unode (FP32 adjoint sweep, table prior: U(z_k) = (1+z_k) I(z_k) of the
+// point's table nodes in FP64) a sample within FP32 reach of a node takes its
+// cell from the FP64 comparison of d_L H0/c with U at that node, so the cell --
+// and with it the slope that the gradient uses -- is the one an FP64
+// evaluation picks.
 template <typename T, int GL, bool GRAD, bool KW = false, bool SPEC = false>
 __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c, const TabView<T>& tv, int lam,
                                             const T* __restrict__ los, int n_z, T inv_dz, int& n_out,
                                             T& lin_out, T* g, T* z_out = nullptr,
-                                            const double* __restrict__ cos64 = nullptr, double dz64 = 0.0) {
+                                            const double* __restrict__ unode = nullptr) {
   static_assert(!(GRAD && KW), "the KDE weights have no adjoint");
   using M = Mth<T>;
   constexpr int NW = Tab<T>::NW;
@@ -168,16 +145,25 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     const T xz = z * inv_dz;
     int kz = (int)xz;
     kz = kz < 0 ? 0 : (kz > n_z - 2 ? n_z - 2 : kz);
+    T fz = xz - (T)kz;
+    los_pair(los, (uint32_t)kz, l0, l1);
     if constexpr (sizeof(T) == 4 && GRAD) {   // (ln L is continuous across nodes; its slope is not)
-      const T fr = xz - (T)(int)xz;
-      if (cos64 && ok && (fr < (T)NODE_TAU * xz || (T)1 - fr < (T)NODE_TAU * xz)) {
+      // within FP32 reach of a node: the cell of the FP64 comparison (the FP32
+      // cell is loaded first, so the common path waits for no decision; another
+      // cell is loaded again)
+      if (unode && ok && (fz < (T)NODE_TAU * xz || (T)1 - fz < (T)NODE_TAU * xz)) {
+        int kn = kz + (fz < (T)0.5 ? 0 : 1);   // the nearest node
+        kn = kn > n_z - 1 ? n_z - 1 : kn;
         const double u64 = ((double)sp.dlc + (double)sp.dlc_lo) * ((double)c.H0 + (double)c.H0_lo);
-        const int k64 = (int)floor(z_fp64(u64, (double)z, cos64) / dz64);
-        kz = k64 < 0 ? 0 : (k64 > n_z - 2 ? n_z - 2 : k64);
+        int k64 = u64 >= unode[kn] ? kn : kn - 1;   // z >= z_kn in FP64
+        k64 = k64 < 0 ? 0 : (k64 > n_z - 2 ? n_z - 2 : k64);
+        if (k64 != kz) {
+          kz = k64;
+          fz = xz - (T)kz;
+          los_pair(los, (uint32_t)kz, l0, l1);
+        }
       }
     }
-    const T fz = xz - (T)kz;
-    los_pair(los, (uint32_t)kz, l0, l1);
     losv = l0 + fz * (l1 - l0);
   } else {
     losv = I * I * rE;
@@ -198,13 +184,18 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T t1 = mp1 * c.inv_dm;
   // a window of zero width is a step at m_min: rho then has the closed form above M = m_min
   const bool inwin = c.dm > (T)0 && t1 < (T)1;
-  const T xw = t1 * (T)NW;
-  int kw = (int)xw;
-  kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);
-  const T tw = xw - (T)kw;
-  const auto Wa = tv.win[kw * GL + lam];
-  const auto Wb = tv.win[(kw + 1) * GL + lam];
-  const T rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
+  // (the window's work is skipped by the whole wavefront when none of its
+  // lanes is in the window: a uniform branch)
+  T rho_w = 0;
+  if (__ballot(inwin)) {
+    const T xw = t1 * (T)NW;
+    int kw = (int)xw;
+    kw = kw < 0 ? 0 : (kw > NW - 1 ? NW - 1 : kw);
+    const T tw = xw - (T)kw;
+    const auto Wa = tv.win[kw * GL + lam];
+    const auto Wb = tv.win[(kw + 1) * GL + lam];
+    rho_w = hermite<T>(tw, Wa.x, Wa.y, Wb.x, Wb.y);
+  }
   // ell2 = log2(m1 / M) above the window.  Near the window's edge, where rho is
   // about Z_w/M^s + ln(m1/M), it comes from m1 - M (carried with m_min's
   // rounding residual) as 2 atanh(x / (2 + x)), x = m1/M - 1 (series to x^9:
@@ -224,10 +215,12 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   // Smoothing of m2: S = 1/(1 + 2^Y) in window.
   const T mp2 = (m2 - c.mmin) - c.mmin_lo;
   const bool w2 = mp2 < c.dm;
-  const T mq = mp2 * (mp2 - c.dm);
-  const T rq = M::rcp(mq);
-  const T Y = w2 ? c.dm * ((T)2 * mp2 - c.dm) * rq * (T)LOG2E : (T)(-1e30);
-  const T aS = M::exp2(-fabs(Y));
+  T rq = 0, Y = (T)(-1e30), aS = 0;   // above the window: S = 1
+  if (__ballot(w2)) {
+    rq = M::rcp(mp2 * (mp2 - c.dm));
+    Y = w2 ? c.dm * ((T)2 * mp2 - c.dm) * rq * (T)LOG2E : (T)(-1e30);
+    aS = M::exp2(-fabs(Y));
+  }
   const T Sf = (T)1 + aS;
   // Total: w = 2^E * los * mix / (Dp * Xf * rho * Sf).
   // (KW: without psi/(1+z), whose (1+z)^(gamma-1) shares gm3 with the Jacobian's (1+z)^-2)

@@ -23,15 +23,13 @@ constexpr int NW_F64 = 256;
 constexpr int NWG_F32 = NW_F32 / 2;
 constexpr int NWG_F64 = NW_F64 / 2;
 
-// Per-point FP64 cosmology record of the FP32 sweep: Omega_m, the panel width,
-// z_max and I(z) at the starts of KZ_I uniform panels over [0, z_max] and at
-// z_max (prefix sums of 8-point Gauss-Legendre), for the FP64 redshift of
-// samples near a redshift-table node.
+// I(z) is tabulated at the starts of KZ_I uniform panels over [0, z_max] and
+// at z_max (prefix sums of 8-point Gauss-Legendre), in FP64.
 constexpr int KZ_I = 256;
-constexpr int COS64_N = 3 + KZ_I + 1;
 // A sample whose table coordinate z/dz lies within this relative distance of
-// a node takes its cell from its FP64 redshift (FP32 redshifts are within
-// 3.2e-7 of it).
+// a node takes its cell from an FP64 comparison (FP32 redshifts are within
+// 3.2e-7 of the FP64 ones): d_L H0/c against U(z_k) = (1+z_k) I(z_k) at the
+// node, U increasing, so the cell is the one of the FP64 redshift.
 constexpr float NODE_TAU = 8e-7f;
 
 constexpr int R_SENTINEL = -(1 << 20);   // "no weight yet" binary exponent
@@ -117,7 +115,7 @@ struct SweepArgs {
   const void* sky;           // [n_z] of T
   int32_t n_z;
   double z_max;
-  const double* cos64;       // [B][COS64_N] FP64 cosmology records (FP32 sweep), or null
+  const double* unode;       // [B][n_z] FP64 U(z_k) = (1+z_k) I(z_k) at the table nodes (FP32 adjoint), or null
   const WorkItem* items;     // in slot order
   const int32_t* order;      // processing order of items
   int32_t n_items;

@@ -64,6 +64,19 @@ __device__ inline double log_dPhi(double mu, double sig, double lo, double hi) {
   return log(d);
 }
 
+// In-place inclusive scan of n_seg segments of n entries each, x[seg * n + i],
+// by the whole workgroup (Hillis-Steele: a fixed shape, so the sums do not
+// depend on timing).  tmp holds n_seg * n entries.
+__device__ void block_scan(double* x, int n, int n_seg, double* tmp) {
+  const int tot = n * n_seg;
+  for (int off = 1; off < n; off <<= 1) {
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) tmp[i] = (i % n) >= off ? x[i - off] : 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) x[i] += tmp[i];
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // setup: per-Lambda constants and tables (FP64), two workgroups per point
 // ---------------------------------------------------------------------------
@@ -75,7 +88,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
                                                     typename V2<T>::t* __restrict__ win_tab,
                                                     typename V2<T>::t* __restrict__ win_grad_tab,
                                                     int* __restrict__ valid_out, double* __restrict__ gmap,
-                                                    double* __restrict__ cos64) {
+                                                    double* __restrict__ unode, int n_z) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW, NWG = Tab<T>::NWG;
   const int b = blockIdx.x;
@@ -112,21 +125,10 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
       }
       Itab[k + 1] = sacc;
     }
+    __shared__ double scan_tmp[KZ];
+    if (tid == 0) Itab[0] = 0.0;
     __syncthreads();
-    if (tid == 0) {
-      Itab[0] = 0.0;
-      for (int k = 1; k <= KZ; ++k) Itab[k] += Itab[k - 1];
-    }
-    __syncthreads();
-    if (cos64) {   // the FP64 record of the point (FP32 sweep: redshifts near table nodes)
-      double* rec = cos64 + (size_t)b * COS64_N;
-      for (int k = tid; k <= KZ; k += blockDim.x) rec[3 + k] = Itab[k];
-      if (tid == 0) {
-        rec[0] = Om;
-        rec[1] = hz;
-        rec[2] = z_max;
-      }
-    }
+    block_scan(Itab + 1, KZ, 1, scan_tmp);
     // I(z) = Itab[k] + 8-point Gauss-Legendre over [z_k, z]
     auto I_at = [&](double z) {
       int k = (int)(z / hz);
@@ -136,6 +138,13 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
       for (int q = 0; q < 8; ++q) sacc += GL8_W[q] / E_of(a + 0.5 * h * (GL8_X[q] + 1.0), Om);
       return Itab[k] + 0.5 * h * sacc;
     };
+    if (unode) {   // U(z_k) = (1+z_k) I(z_k) at the redshift-table nodes (FP32 adjoint)
+      const double dzn = z_max / (double)(n_z - 1);
+      for (int k = tid; k < n_z; k += blockDim.x) {
+        const double zk = k * dzn;
+        unode[(size_t)b * n_z + k] = ok ? (1.0 + zk) * I_at(zk) : 0.0;
+      }
+    }
     // --- inverse distance table: y(v) = z/u at v_k = 1 + k h_v, u = (v^2-1)/4.
     const double umax = ok ? (1.0 + z_max) * Itab[KZ] : 1.0;
     const double vmax = sqrt(1.0 + 4.0 * umax);
@@ -257,16 +266,22 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
     qsum[3][i] = a3;
   }
   __syncthreads();
-  // running sums over the panels (each panel's quarters in order): one lane per array
+  // running sums over the panels of the four arrays (each panel's quarters
+  // summed in order, then a block scan)
+  __shared__ double pan[4 * NW], pan_tmp[4 * NW];
+  for (int i = tid; i < 4 * NW; i += blockDim.x) {
+    const double* src = qsum[i / NW] + 4 * (i % NW);
+    pan[i] = (src[0] + src[1]) + (src[2] + src[3]);
+  }
+  __syncthreads();
+  block_scan(pan, NW, 4, pan_tmp);
+  for (int i = tid; i < 4 * (NW + 1); i += blockDim.x) {
+    const int a = i / (NW + 1), j = i % (NW + 1);
+    double* dst = a == 0 ? cum : cumg[a - 1];
+    dst[j] = j == 0 ? 0.0 : pan[a * NW + j - 1];
+  }
   if (tid < 4) {
-    double* dst = tid == 0 ? cum : cumg[tid - 1];
-    const double* src = qsum[tid];
-    double run = 0.0;
-    dst[0] = 0.0;
-    for (int j = 0; j < NW; ++j) {
-      run += (src[4 * j] + src[4 * j + 1]) + (src[4 * j + 2] + src[4 * j + 3]);
-      dst[j + 1] = run;
-    }
+    const double run = pan[tid * NW + NW - 1];
     // With delta_m = 0 the window integrals vanish, but two of their derivatives
     // do not: the window integral of m^beta S is m_min^beta delta_m / 2 to first
     // order (the window's mean over its width is 1/2), and the step at m_min
@@ -462,7 +477,7 @@ template <typename T, int GL, bool GRAD, bool SPEC, typename AccT>
 __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
                                           bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
                                           const T* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
-                                          T* g, const double* __restrict__ cos64, double dz64) {
+                                          T* g, const double* __restrict__ unode) {
   constexpr int NS = 64 / GL;
   if (s1 <= s0) return;
   // indices are clamped into the run; with several samples per wavefront two
@@ -482,7 +497,7 @@ __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int6
     if (sb + sg < s1 && live) {
       int n;
       T lin;
-      eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g, nullptr, cos64, dz64);
+      eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, n, lin, g, nullptr, unode);
       acc.template add<T>(n, lin, g);
     }
   }
@@ -545,9 +560,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
   const T* __restrict__ los = reinterpret_cast<const T*>(a.los);
   const T* __restrict__ sky = reinterpret_cast<const T*>(a.sky);
-  // the point's FP64 record (FP32 table prior only): cells of samples near table nodes
-  const double* __restrict__ rec64 = (a.cos64 && !SPEC && active) ? a.cos64 + (size_t)b * COS64_N : nullptr;
-  const double dz64 = a.z_max / (double)(a.n_z - 1);
+  // the point's FP64 node values (FP32 table prior only): cells of samples near table nodes
+  const double* __restrict__ un = (a.unode && !SPEC && active) ? a.unode + (size_t)b * a.n_z : nullptr;
   T g[GRAD ? 16 : 1];
 
   for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
@@ -561,7 +575,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
       const T* __restrict__ tab = SPEC ? nullptr : los + (size_t)a.pix_row[w.pix0] * a.n_z;
       PixAcc<GRAD, T> pix;
       pix.zero();
-      sweep_run<T, GL, GRAD, SPEC>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, rec64, dz64);
+      sweep_run<T, GL, GRAD, SPEC>(samp, w.s0, w.s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, un);
 #pragma unroll
       for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
       chunk.merge(pix);
@@ -571,7 +585,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
         const T* __restrict__ tab = SPEC ? nullptr : los + (size_t)a.pix_row[p] * a.n_z;
         PixAcc<GRAD, T> pix;
         pix.zero();
-        sweep_run<T, GL, GRAD, SPEC>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, rec64, dz64);
+        sweep_run<T, GL, GRAD, SPEC>(samp, s0, s1, sg, live, c, tv, lam, tab, a.n_z, inv_dz, pix, g, un);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         bool pass;
@@ -590,7 +604,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
         pix.zero();
         const int64_t v1 = v0 + VP < w.s1 ? v0 + VP : w.s1;
         sweep_run<T, GL, GRAD, SPEC>(inj, v0, v1, sg, live, c, tv, lam, SPEC ? nullptr : sky, a.n_z, inv_dz,
-                               pix, g, rec64, dz64);
+                               pix, g, un);
 #pragma unroll
         for (int off = GL; off < 64; off <<= 1) pix.xor_merge(off);
         chunk.merge(pix);
@@ -612,40 +626,56 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
 }
 
 // ---------------------------------------------------------------------------
-// gate of split pixels: merge the parts (in slot order), apply Eq. (8), write
-// the result into the first part's slot and clear the others.
+// gate of split pixels: one wavefront per (split pixel, point) merges the
+// parts (lanes stride over them, then a fixed xor butterfly of exact power-of-
+// two rescalings and commutative sums, so every lane holds the same bits),
+// applies Eq. (8), writes the result into the first part's slot and clears
+// the others.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gate_split_kernel(GateSplitArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)a.n_split * a.B) return;
-  const int sp = (int)(i / a.B), b = (int)(i % a.B);
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= (int64_t)a.n_split * a.B) return;   // whole wavefronts
+  const int sp = (int)(w / a.B), b = (int)(w % a.B);
   const SplitPix s = a.splits[sp];
   auto at = [&](int slot, int f) -> double& { return a.part[((size_t)b * a.n_items + slot) * a.nf + f]; };
+  const int ng = a.nf - 4;
   double R = -1e300, S1 = 0, S2 = 0;
   double G[16];
   for (int p = 0; p < 16; ++p) G[p] = 0;
-  const int ng = a.nf - 4;
-  for (int k = 0; k < s.n_parts; ++k) {
-    const int sl = s.slot0 + k;
-    const double s1 = at(sl, 1);
-    if (!(s1 > 0)) continue;
-    const double r = at(sl, 0);
-    if (r > R) {
-      const int d = (R > -1e299) ? (int)(R - r) : -2000;
-      S1 = ldexp(S1, d);
-      S2 = ldexp(S2, 2 * d);
-      for (int p = 0; p < ng; ++p) G[p] = ldexp(G[p], d);
+  // (R, S1, S2, G) += 2^(r - R) (r, s1, s2, g): rescaled to the larger exponent
+  auto merge = [&](double r, double s1, double s2, const double* g) {
+    if (!(s1 > 0)) return;
+    if (!(S1 > 0)) {
       R = r;
+      S1 = s1;
+      S2 = s2;
+      for (int p = 0; p < ng; ++p) G[p] = g[p];
+      return;
     }
-    const int d = (int)(r - R);
-    S1 += ldexp(s1, d);
-    S2 += ldexp(at(sl, 2), 2 * d);
-    for (int p = 0; p < ng; ++p) G[p] += ldexp(at(sl, 4 + p), d);
+    const double Rm = fmax(R, r);
+    const int da = (int)(R - Rm), db = (int)(r - Rm);
+    S1 = ldexp(S1, da) + ldexp(s1, db);
+    S2 = ldexp(S2, 2 * da) + ldexp(s2, 2 * db);
+    for (int p = 0; p < ng; ++p) G[p] = ldexp(G[p], da) + ldexp(g[p], db);
+    R = Rm;
+  };
+  for (int k = lane; k < s.n_parts; k += 64) {
+    const int sl = s.slot0 + k;
+    double g[16];
+    for (int p = 0; p < ng; ++p) g[p] = at(sl, 4 + p);
+    merge(at(sl, 0), at(sl, 1), at(sl, 2), g);
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    double g[16];
+    for (int p = 0; p < ng; ++p) g[p] = __shfl_xor(G[p], off);
+    const double r = __shfl_xor(R, off), s1 = __shfl_xor(S1, off), s2 = __shfl_xor(S2, off);
+    merge(r, s1, s2, g);
   }
   bool pass;
   if (a.gate_mode == 2) pass = S1 > 0;
   else pass = S2 > 0 && S1 * S1 >= a.neff_min * S2;
-  for (int k = 0; k < s.n_parts; ++k) {
+  for (int k = lane; k < s.n_parts; k += 64) {
     const int sl = s.slot0 + k;
     const bool first = k == 0 && pass;
     at(sl, 0) = first ? R : (double)R_SENTINEL;
@@ -958,21 +988,25 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   }
 }
 
-// Merge of the slices of one point in slice order (one thread per point).
+// Merge of the slices of one point: one wavefront per point, lane k takes
+// slices k, k + 64, ..., then a fixed xor butterfly.  Its sums are commutative
+// and its selection merges exact power-of-two rescalings, so every lane ends
+// with the same bits and the result does not depend on timing.
 template <bool GRAD>
 __global__ __launch_bounds__(64) void combine_slices_kernel(CombineArgs a, int n_slices) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.B) return;
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
   double acc = 0, nused = 0;
-  unsigned int fl = 0;
+  int fl = 0;
   Part3 sel{0, 0, 0};
   double G[GRAD ? 16 : 1], Gs[GRAD ? 16 : 1];
+#pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = Gs[p] = 0;
-  for (int sl = 0; sl < n_slices; ++sl) {
+  for (int sl = lane; sl < n_slices; sl += 64) {
     const double* o = a.cpart + ((size_t)b * n_slices + sl) * NF_CSLICE;
     acc += o[0];
     nused += o[1];
-    fl |= (unsigned int)o[2];
+    fl |= (int)o[2];
     const Part3 x{o[3], o[4], o[5]};
     if constexpr (GRAD) {
       for (int p = 0; p < 16; ++p) G[p] += o[6 + p];
@@ -985,7 +1019,25 @@ __global__ __launch_bounds__(64) void combine_slices_kernel(CombineArgs a, int n
     }
     sel = pmerge(sel, x);
   }
-  combine_finish<GRAD>(a, b, acc, nused, fl, G, 1, sel, Gs, 1);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    acc += __shfl_xor(acc, off);
+    nused += __shfl_xor(nused, off);
+    fl |= __shfl_xor(fl, off);
+    const Part3 o{__shfl_xor(sel.R, off), __shfl_xor(sel.S1, off), __shfl_xor(sel.S2, off)};
+    if constexpr (GRAD) {
+      const bool hs = sel.S1 > 0, ho = o.S1 > 0;
+      const double Rm = hs && ho ? fmax(sel.R, o.R) : (hs ? sel.R : o.R);
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        G[p] += __shfl_xor(G[p], off);
+        const double go = __shfl_xor(Gs[p], off);
+        Gs[p] = (hs ? ldexp(Gs[p], (int)(sel.R - Rm)) : 0.0) + (ho ? ldexp(go, (int)(o.R - Rm)) : 0.0);
+      }
+    }
+    sel = pmerge(sel, o);
+  }
+  if (lane == 0) combine_finish<GRAD>(a, b, acc, nused, (unsigned int)fl, G, 1, sel, Gs, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1032,15 +1084,15 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 
 // threads: per workgroup, 256 ... SETUP_THREADS (the loops stride by the block size).
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
-                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* cos64, int threads,
-                        hipStream_t st) {
+                        void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* unode, int n_z,
+                        int threads, hipStream_t st) {
   if (threads < 256 || threads > SETUP_THREADS || threads % 64) return hipErrorInvalidValue;
   if (fp32)
     setup_kernel<float><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
-                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap, cos64);
+                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap, unode, n_z);
   else
     setup_kernel<double><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
-                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap, cos64);
+                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap, unode, n_z);
   return hipGetLastError();
 }
 
@@ -1099,7 +1151,7 @@ hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int gri
 
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
   if (a.n_split == 0) return hipSuccess;
-  const int64_t n = (int64_t)a.n_split * a.B;
+  const int64_t n = (int64_t)a.n_split * a.B * 64;   // one wavefront per (split pixel, point)
   gate_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a);
   return hipGetLastError();
 }
@@ -1125,8 +1177,8 @@ hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
   if (a.n_slices > 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (grad && !a.kde) combine_slices_kernel<true><<<(a.B + 63) / 64, 64, 0, st>>>(a, a.n_slices);
-    else combine_slices_kernel<false><<<(a.B + 63) / 64, 64, 0, st>>>(a, a.n_slices);
+    if (grad && !a.kde) combine_slices_kernel<true><<<a.B, 64, 0, st>>>(a, a.n_slices);
+    else combine_slices_kernel<false><<<a.B, 64, 0, st>>>(a, a.n_slices);
   }
   return hipGetLastError();
 }
