@@ -216,6 +216,26 @@ int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_log
                      double* d_neff_sel, uint32_t* d_flags, void* stream);
 
 /*
+ * dsl_loglike_grad without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving or sampling loops,
+ * harnesses that forbid hipMalloc.  Arguments, outputs and results are those of
+ * dsl_loglike_grad (Monte Carlo numerator only).  The call allocates nothing,
+ * copies nothing from the host and captures no graph: its workspace (per-point
+ * tables, per-item partial sums, combine records) lives in one static device
+ * array of 64 MiB per GPU, held by the library until the process ends, and the
+ * handle's current work list is used as it stands.  A batch whose workspace
+ * exceeds 64 MiB returns DSL_EINVAL (e.g. the 5000-event catalogue with 64
+ * points needs about 0.75 GB: use dsl_loglike_grad there).  Every call on one
+ * GPU shares that array, from every handle: calls that overlap in time on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller; the array keeps the last call's contents (nothing in it needs to
+ * start at zero).
+ */
+int dsl_loglike_grad_noalloc(dsl_handle* h, const double* d_lambda, int B, double* d_logL,
+                             double* d_grad, double* d_logL_event, double* d_neff_event,
+                             double* d_neff_sel, uint32_t* d_flags, void* stream);
+
+/*
  * Choose the sweep configuration (Lambda tile, chunk) for batches of B points
  * by timing the candidates on the current device; the choice is cached in the
  * handle and, when cache_path is not NULL, appended to that text file (one

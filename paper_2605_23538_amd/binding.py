@@ -66,6 +66,8 @@ def load_library(path: Optional[str] = None):
     lib.dsl_loglike.restype = i32
     lib.dsl_loglike_grad.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.dsl_loglike_grad.restype = i32
+    lib.dsl_loglike_grad_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.dsl_loglike_grad_noalloc.restype = i32
     lib.dsl_autotune.argtypes = [vp, i32, i32, C.c_char_p]
     lib.dsl_autotune.restype = i32
     lib.dsl_get_timing.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -235,6 +237,26 @@ class DarkSirenLikelihood:
         if side:
             self._keep([lam, *out.values()], s)
         _check(self.lib, rc, "dsl_loglike_grad")
+        return out
+
+    def loglike_grad_noalloc(self, lam: torch.Tensor, out: dict, stream=None):
+        """loglike_grad into caller-provided device tensors `out` (logL [B], grad
+        [B, 16]; optional logL_event / neff_event [B, n_events], neff_sel [B],
+        flags [B] int32), through the entry point that allocates no device memory
+        (its workspace is the library's static per-GPU scratch).  `lam` must be a
+        contiguous float64 [B, 16] tensor on the handle's device."""
+        if lam.dtype != torch.float64 or not lam.is_contiguous() or lam.dim() != 2 or lam.shape[1] != 16:
+            raise ValueError("lam must be a contiguous float64 [B, 16] device tensor")
+        B = lam.shape[0]
+        dev = lam.device
+        s, side = self._stream(stream, dev)
+        rc = self.lib.dsl_loglike_grad_noalloc(
+            self.h, _ptr(lam), B, _ptr(out["logL"]), _ptr(out["grad"]), _ptr(out.get("logL_event")),
+            _ptr(out.get("neff_event")), _ptr(out.get("neff_sel")), _ptr(out.get("flags")),
+            C.c_void_p(s.cuda_stream))
+        if side:
+            self._keep([lam, *out.values()], s)
+        _check(self.lib, rc, "dsl_loglike_grad_noalloc")
         return out
 
     def __call__(self, lam: torch.Tensor) -> torch.Tensor:

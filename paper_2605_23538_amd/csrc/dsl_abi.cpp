@@ -11,6 +11,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -147,6 +148,7 @@ struct dsl_handle {
   hipEvent_t done = nullptr;
   bool pending = false;
   hipStream_t cap_stream = nullptr;
+  void* scratch = nullptr;   // device address of the static scratch array on this handle's device
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::vector<const void*> ws_sig;   // workspace addresses the cached graphs were captured with
   std::map<std::pair<int, int>, SweepCfg> tuned;   // (B, grad) -> configuration
@@ -160,7 +162,33 @@ struct dsl_handle {
   }
 };
 
+// Workspace of the allocation-free entry point (dsl_loglike_grad_noalloc): one
+// static device array per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress returns, looked up
+// once per device with that device current.
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+// The scratch array's address on `device`, which must be the current device.
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(DSL_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    if (!ptr) return fail(DSL_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    it = g_scratch_ptr.emplace(device, ptr).first;
+  }
+  *out = it->second;
+  return DSL_OK;
+}
 
 // Wait until the last call on this handle has finished on the device.
 int quiesce(dsl_handle* h) {
@@ -546,7 +574,8 @@ bool merge_events(const dsl_handle* h) {
   return h->numerator == 0 && h->n_events > 0 && h->inj_slot0 >= 16 * h->n_events;
 }
 
-// Device workspace of one call: the handle's buffers.
+// Device workspace of one call: the handle's buffers, or (for the
+// allocation-free entry point) ranges of the per-device static scratch.
 struct Ws {
   void* lamc = nullptr;
   void* cos_tab = nullptr;
@@ -818,6 +847,42 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   return er == hipSuccess ? DSL_OK : hipfail(er, "hipEventRecord");
 }
 
+// The allocation-free variant of run() (gradient entry point): the workspace is
+// carved out of the device's static scratch array; the work list in place is
+// used whatever chunk it was built for (the chunk only sets how the sums are
+// cut into items); no graph, no timing events, no host-to-device copy.
+int run_noalloc(dsl_handle* h, const double* d_lambda, int B, const CallOut& o, hipStream_t st) {
+  if (!h) return fail(DSL_ESTATE, "handle is NULL");
+  (void)hipGetLastError();
+  if (!d_lambda || !o.logL || !o.grad) return fail(DSL_EINVAL, "NULL device pointer");
+  if (B < 1 || B > h->max_batch) return fail(DSL_EINVAL, "B out of range [1, max_batch]");
+  if (h->numerator == 1) return fail(DSL_EINVAL, "the KDE numerator has no gradient (use numerator 0)");
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != h->device) return fail(DSL_ESTATE, "current device differs from the handle's device");
+  if (!h->scratch || h->built_chunk < 0) return fail(DSL_ESTATE, "handle has no scratch address or work list");
+  SweepCfg cfg = config_for(h, B, true);
+  cfg.chunk = h->built_chunk;
+  h->last_gl = cfg.GL;
+  Ws ws;
+  const WsNeeds need = workspace_needs(h, B, true, ws);
+  size_t off = 0;
+  for (const WsNeed& w : need) {
+    off = (off + 255) & ~(size_t)255;
+    if (w.bytes > SCRATCH_BYTES || off + w.bytes > SCRATCH_BYTES)
+      return fail(DSL_EINVAL, "this batch needs more than the " + std::to_string(SCRATCH_BYTES >> 20) +
+                                  " MiB scratch of the allocation-free entry point (use dsl_loglike_grad)");
+    *w.dst = static_cast<unsigned char*>(h->scratch) + off;
+    off += w.bytes;
+  }
+  const int rc = enqueue(h, ws, d_lambda, B, true, o, cfg, st, false);
+  // a later call that rewrites the work list waits for this one
+  const hipError_t er = hipEventRecord(h->done, st);
+  if (er == hipSuccess) h->pending = true;
+  if (rc) return rc;
+  return er == hipSuccess ? DSL_OK : hipfail(er, "hipEventRecord");
+}
+
 // Sweep configurations the autotuner may choose for batches of B points:
 // Lambda tiles (a tile is skipped when it would leave most lanes idle), chunks
 // about the automatic size, and for the FP32 adjoint both workgroup shapes.
@@ -986,6 +1051,10 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIPCHK(init_kernel_attrs());
   HIPCHK(init_kde_attrs());
+  if ((rc = scratch_address(h->device, &h->scratch))) return rc;
+  // a work list from the start (the one-point configuration's), so that the
+  // allocation-free entry point always has one to read
+  if ((rc = build_items(h.get(), config_for(h.get(), 1, false).chunk))) return rc;
   *out = h.release();
   return DSL_OK;
 }
@@ -1113,6 +1182,13 @@ int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_log
                      void* stream) {
   CallOut o{d_logL, d_grad, d_logL_event, d_neff_event, d_neff_sel, d_flags};
   return run(h, d_lambda, B, true, o, (hipStream_t)stream);
+}
+
+int dsl_loglike_grad_noalloc(dsl_handle* h, const double* d_lambda, int B, double* d_logL, double* d_grad,
+                             double* d_logL_event, double* d_neff_event, double* d_neff_sel, uint32_t* d_flags,
+                             void* stream) {
+  CallOut o{d_logL, d_grad, d_logL_event, d_neff_event, d_neff_sel, d_flags};
+  return run_noalloc(h, d_lambda, B, o, (hipStream_t)stream);
 }
 
 int dsl_get_timing(dsl_handle* h, float* ms_setup, float* ms_sweep, float* ms_combine) {
