@@ -461,7 +461,11 @@ def _event_terms(cat, ev_ids, L: Lam, opt: Options, margin_out=None):
             wk = torch.exp(lw.detach() - lE1.detach()[ev_seg][seg])
             use = passing[seg] & torch.isfinite(wk)
             ev_cond = torch.zeros(nE, dtype=DT).index_add(0, ev_seg[seg], torch.where(use, wk * cond, torch.zeros_like(cond)))
-            margin_out.append((ev_gate.numpy(), ev_samp.numpy(), pix, gm.numpy(), ev_cond.numpy()))
+            # and of ln N_eff,i = 2 ln S1 - ln S2: d ln N_eff / d ln w_k = 2 w_k/S1 - 2 w_k^2/S2
+            wk2 = torch.exp(2.0 * lw.detach() - lE2.detach()[ev_seg][seg])
+            ncond = torch.abs(2.0 * wk - 2.0 * wk2) * cond
+            ev_ncond = torch.zeros(nE, dtype=DT).index_add(0, ev_seg[seg], torch.where(use, ncond, torch.zeros_like(cond)))
+            margin_out.append((ev_gate.numpy(), ev_samp.numpy(), pix, gm.numpy(), ev_cond.numpy(), ev_ncond.numpy()))
     return lnL, neff_ev
 
 
@@ -492,7 +496,8 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     ids) inverts the gate decision of those pixels, so such a test can evaluate
     the other outcome.  event_fp32_cond[n_events] bounds, to first order, how
     far ln L_i moves when every sample's d_L is perturbed by 3.2e-7 and its
-    masses by 6e-8 (relative): the reach of an FP32 evaluation of the inputs.
+    masses by 6e-8 (relative): the reach of an FP32 evaluation of the inputs;
+    event_fp32_cond_neff[n_events] bounds the relative change of N_eff,i alike.
     """
     lam_np = np.asarray(lam, dtype=np.float64).reshape(16)
     nE = cat.n_events
@@ -513,6 +518,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
     samp_m = np.empty(nE)
     pix_m = np.full(cat.n_pix, math.inf) if margins else None
     ev_cond = np.zeros(nE)
+    ev_ncond = np.zeros(nE)
     for b0 in range(0, nE, event_block):
         ids = np.arange(b0, min(nE, b0 + event_block))
         mo = [] if margins else None
@@ -523,7 +529,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         lnL_ev[ids] = lnL_b.detach().numpy()
         neff_ev[ids] = neff_b.numpy()
         if margins:
-            gate_m[ids], samp_m[ids], pix_b, pm_b, ev_cond[ids] = mo[0]
+            gate_m[ids], samp_m[ids], pix_b, pm_b, ev_cond[ids], ev_ncond[ids] = mo[0]
             pix_m[pix_b] = pm_b
     # Selection term: alpha = (1/N_draw) sum_n w_n, merged over chunks.
     lc1, lc2, gc = [], [], []
@@ -566,6 +572,7 @@ def loglike(cat, lam, neff_min: float = 2.0, gate_mode: int = 0, grad: bool = Fa
         out["inj_margin"] = inj_margin
         out["pixel_gate_margin"] = pix_m
         out["event_fp32_cond"] = ev_cond
+        out["event_fp32_cond_neff"] = ev_ncond
     return out
 
 
@@ -712,7 +719,7 @@ def _pixel_kde_term(z, lw, h, table, z_max, L: Lam, n_grid):
 
 
 def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff_min: float = 2.0,
-                gate_mode: int = 0, grad: bool = False, margins: bool = False):
+                gate_mode: int = 0, grad: bool = False, margins: bool = False, gate_flip=None):
     """Oracle log-likelihood with the paper's KDE numerator.
 
     For every pixel j of event i: the in-support samples (d_L <= d_L(z_max))
@@ -722,6 +729,9 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
     rule on kde_grid); the pixel passes Eq. (8) on the same weights; and
     L_i = (1/N_s,i) sum_pass T_j.  The selection term is the Monte Carlo sum
     over injections, exactly as in loglike.  Pure-Python loop over pixels.
+    margins and gate_flip as in loglike (pixel_gate_margin[n_pix]: the distance
+    of each pixel's ln N_eff from ln N_min; gate_flip inverts those pixels'
+    Eq. (8) decisions).
     """
     lam_np = np.asarray(lam, dtype=np.float64).reshape(16)
     nE = cat.n_events
@@ -739,6 +749,8 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
     neff_ev = np.empty(nE)
     gate_m = np.full(nE, math.inf)
     samp_m = np.full(nE, math.inf)
+    pix_m = np.full(cat.n_pix, math.inf)
+    flips = set() if gate_flip is None else set(int(p) for p in np.asarray(gate_flip).reshape(-1))
     g_ev = torch.zeros(16, dtype=DT)
     umax = (1.0 + cat.z_max) * float(comoving_integral(torch.tensor(cat.z_max, dtype=DT), torch.tensor(lam_np[1])))
     with torch.set_grad_enabled(grad):
@@ -762,7 +774,11 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
                 lneff = float(2.0 * l1 - l2) if math.isfinite(float(l1)) else -math.inf
                 if margins and math.isfinite(lneff):
                     gate_m[i] = min(gate_m[i], abs(lneff - log_nmin))
-                if not math.isfinite(float(l1)) or (gate_mode != 2 and lneff < log_nmin):
+                    pix_m[j] = abs(lneff - log_nmin)
+                passes = gate_mode == 2 or lneff >= log_nmin
+                if gate_mode != 2 and j in flips:   # the other outcome of the Eq. (8) test
+                    passes = not passes
+                if not math.isfinite(float(l1)) or not passes:
                     continue
                 h = bw(z)
                 table = torch.from_numpy(np.asarray(cat.los[int(cat.pix_los_row[j])], dtype=np.float64))
@@ -814,6 +830,7 @@ def loglike_kde(cat, lam, bandwidth: str = "scott", n_grid: int = KDE_GRID, neff
     if margins:
         out["gate_margin"] = gate_m
         out["sample_margin"] = samp_m
+        out["pixel_gate_margin"] = pix_m
     return out
 
 

@@ -6,7 +6,8 @@ paper_2605_23538_amd.synth) is evaluated by the FP64 oracle alone for points of
 the benchmark's 64-point batch: every event's ln L_i and N_eff,i, ln alpha,
 N_eff of the selection term, ln L and the 16-entry gradient (Sec. II A,
 Eqs. 3-5, 7, 8), with the per-event margins of the gate and support decisions
-and each event's sensitivity to its inputs at FP32 reach (event_fp32_cond).
+and each event's sensitivity to its inputs at FP32 reach (event_fp32_cond for
+ln L_i, event_fp32_cond_neff for the relative N_eff,i).
 
 A pixel whose ln N_eff lies within AMB of ln N_min is a decision that a path
 working in another precision may take the other way (Eq. 8).  For every event
@@ -97,6 +98,7 @@ def main():
                 grad=np.asarray(r["grad"], np.float64), logL_event=np.asarray(r["logL_event"], np.float64),
                 neff_event=np.asarray(r["neff_event"], np.float64),
                 event_fp32_cond=np.asarray(r["event_fp32_cond"], np.float64),
+                event_fp32_cond_neff=np.asarray(r["event_fp32_cond_neff"], np.float64),
                 gate_margin=np.asarray(r["gate_margin"], np.float32),
                 sample_margin=np.asarray(r["sample_margin"], np.float32),
                 inj_margin=np.float64(r["inj_margin"]), amb_margin=np.float64(AMB),

@@ -387,6 +387,40 @@ def test_gate_flip_and_pixel_margins_bruteforce(flip):
     np.testing.assert_allclose(r["pixel_gate_margin"], want, rtol=1e-9, atol=1e-12)
 
 
+def test_kde_gate_flip_of_the_failing_pixels_is_the_ungated_likelihood():
+    """The KDE oracle's other-outcome hook: inverting the Eq. (8) decision of
+    exactly the pixels that fail it passes every pixel with weight, which is
+    the likelihood with the gate disabled (gate_mode 2); its per-pixel margins
+    are |ln N_eff - ln 2| of those pixels."""
+    cat = synth.make_catalog("c1", n_events=3, n_inj=400)
+    lam = synth.lam_vector(H0=45.0, Om=0.45, delta_m=8.0, beta=-2.0)
+    base = O.loglike_kde(cat, lam, margins=True)
+    pm = base["pixel_gate_margin"]
+    lneff = []
+    failing = []
+    for j in range(cat.n_pix):
+        s0, s1 = int(cat.pix_samp_off[j]), int(cat.pix_samp_off[j + 1])
+        if s1 == s0:
+            continue
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a[s0:s1], dtype=np.float64))
+        _, inside, lw = O.kde_log_weights(t(cat.m1d), t(cat.m2d), t(cat.dl), t(cat.ln_pi), cat.z_max, O.Lam.of(T(lam)))
+        lw = lw[inside].numpy()
+        if lw.size == 0 or not np.isfinite(lw).any():
+            continue
+        m = lw.max()
+        ln = 2 * (m + math.log(np.exp(lw - m).sum())) - (2 * m + math.log(np.exp(2 * (lw - m)).sum()))
+        lneff.append((j, ln))
+        if ln < math.log(2.0):
+            failing.append(j)
+    assert failing, "the case must have pixels that fail the gate"
+    for j, ln in lneff:
+        assert abs(pm[j] - abs(ln - math.log(2.0))) < 1e-9
+    flipped = O.loglike_kde(cat, lam, gate_flip=failing)
+    ungated = O.loglike_kde(cat, lam, gate_mode=2)
+    np.testing.assert_allclose(flipped["logL_event"], ungated["logL_event"], rtol=1e-12)
+    assert not np.allclose(base["logL_event"], ungated["logL_event"], rtol=1e-9, atol=0)
+
+
 # ---------------------------------------------------------------- invariances
 def test_invariance_H0_distance_rescaling():
     """(d_L, H0) -> (s d_L, H0/s) leaves every redshift unchanged; the Jacobian
@@ -583,16 +617,19 @@ def test_downsample_keeps_cap_per_pixel():
 
 
 def test_event_fp32_condition_bounds_input_perturbations():
-    """The per-event sensitivity the parity tests allow for an FP32 evaluation
-    of the inputs (d_L to 3.2e-7, masses to 6e-8, relative) bounds the change of
-    ln L_i under random perturbations of that size, and is not vacuous."""
+    """The per-event sensitivities the parity tests allow for an FP32 evaluation
+    of the inputs (d_L to 3.2e-7, masses to 6e-8, relative) bound the change of
+    ln L_i and the relative change of N_eff,i under random perturbations of that
+    size, and are not vacuous."""
     rng = np.random.default_rng(11)
     cat = synth.make_catalog("c1", n_events=3, n_inj=500)
     lam = synth.lam_vector(delta_m=0.5, mmin=7.0, beta=6.0, alpha=5.0)
     base = O.loglike(cat, lam, gate_mode=2, margins=True)
     cond = base["event_fp32_cond"]
+    ncond = base["event_fp32_cond_neff"]
     assert np.all(cond > 0) and np.all(np.isfinite(cond))
-    worst = 0.0
+    assert np.all(ncond > 0) and np.all(np.isfinite(ncond))
+    worst = worst_n = 0.0
     for _ in range(3):
         c2 = copy.deepcopy(cat)
         c2.dl = cat.dl * (1 + 3.2e-7 * rng.choice([-1.0, 1.0], cat.n_samp))
@@ -602,4 +639,7 @@ def test_event_fp32_condition_bounds_input_perturbations():
         d = np.abs(r["logL_event"] - base["logL_event"])
         assert np.all(d <= cond * (1 + 1e-3)), (d, cond)
         worst = max(worst, float(np.max(d / cond)))
-    assert worst > 0.01   # the bound is not vacuous
+        dn = np.abs(np.log(r["neff_event"] / base["neff_event"]))
+        assert np.all(dn <= ncond * (1 + 1e-3)), (dn, ncond)
+        worst_n = max(worst_n, float(np.max(dn / ncond)))
+    assert worst > 0.01 and worst_n > 0.01   # the bounds are not vacuous
