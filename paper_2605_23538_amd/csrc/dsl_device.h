@@ -230,7 +230,8 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   const T f = E - En;
   const T eP = M::exp2(tP - mx + f), eL = M::exp2(tL - mx + f), eH = M::exp2(tH - mx + f);
   const T mixf = eP + eL + eH;
-  const T den = KW ? Dp * rho * Sf : Dp * Xf * rho * Sf;
+  const T DX = Dp * Xf, RS = rho * Sf;
+  const T den = KW ? Dp * RS : DX * RS;
   const T rden = M::rcp(den);
   T lin = losv * mixf * rden;
   ok = ok && (lin == lin) && (lin < (T)3.0e38);
@@ -242,10 +243,9 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
     const T Q = M::rcp(losv * mixf);          // 1/(los mix)
     const T rmix = Q * losv, rlos = Q * mixf;
     const T fP = eP * rmix, fL = eL * rmix, fH = eH * rmix;
-    const T rDp = rden * Xf * rho * Sf;      // 1/Dp
-    const T rXf = rden * Dp * rho * Sf;      // 1/Xf
-    const T rrho = rden * Dp * Xf * Sf;      // 1/rho
-    const T rSf = rden * Dp * Xf * rho;      // 1/Sf
+    // 1/Dp, 1/Xf, 1/rho, 1/Sf from the one reciprocal and the pair products
+    const T rRS = rden * RS, rDX = rden * DX;
+    const T rDp = rRS * Xf, rXf = rRS * Dp, rrho = rDX * Sf, rSf = rDX * rho;
     const T lnm1 = lm1 * ln2;
     const T lnq = sp.lq * ln2;
     // rate pieces: sig = X/(1+X)
@@ -390,8 +390,12 @@ struct PixAcc {
   __device__ __forceinline__ void add(int n, T lin, const T* g) {
     if (lin > (T)0) {
       if constexpr (GRAD) {
-        // the first weight also takes this branch (R = R_SENTINEL): the zero sums stay zero
-        if (n > R + RESCALE_MARGIN) rescale(n);
+        // the first weight also takes this branch (R = R_SENTINEL): the sums are
+        // zero, so only the exponent is set
+        if (n > R + RESCALE_MARGIN) {
+          if (R == R_SENTINEL) R = n;
+          else rescale(n);
+        }
       } else {
         if (R == R_SENTINEL) R = n;   // accumulators are zero: no rescale needed
         else if (n > R + RESCALE_MARGIN) rescale(n);
