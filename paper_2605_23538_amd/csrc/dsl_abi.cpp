@@ -26,7 +26,7 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
                        int64_t n, void* out, hipStream_t st);
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
                         void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* unode, int n_z,
-                        int threads, hipStream_t st);
+                        int32_t* item_ctr, int threads, hipStream_t st);
 hipError_t launch_sweep(int fp32, int GL, bool grad, const SweepArgs& a, int grid_x, int threads, hipStream_t st);
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st);
 hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st);
@@ -125,7 +125,8 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, unode, kde_out, kde_ev, kde_evals, cpart, ev_rec;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, unode, item_ctr, kde_out, kde_ev, kde_evals, cpart,
+      ev_rec;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -584,6 +585,7 @@ struct Ws {
   void* valid = nullptr;
   void* gmap = nullptr;
   void* unode = nullptr;   // FP64 (1+z) I(z) at the table nodes (FP32 adjoint)
+  void* item_ctr = nullptr;   // per-tile work-item counters of the sweep
   void* part = nullptr;
   void* cpart = nullptr;
   void* ev_rec = nullptr;
@@ -602,7 +604,7 @@ struct WsNeed {
 };
 
 struct WsNeeds {
-  WsNeed v[14];
+  WsNeed v[15];
   int n = 0;
   void add(DevBuf* b, void** d, size_t bytes, const char* what) { v[n++] = WsNeed{b, d, bytes, what}; }
   const WsNeed* begin() const { return v; }
@@ -624,6 +626,7 @@ WsNeeds workspace_needs(dsl_handle* h, int B, bool grad, Ws& ws) {
   n.add(&h->valid, &ws.valid, sizeof(int) * Bz, "valid");
   n.add(&h->gmap, &ws.gmap, sizeof(double) * N_GMAP * Bz, "gmap");
   if (h->fp32 && grad) n.add(&h->unode, &ws.unode, sizeof(double) * (size_t)h->n_z * Bz, "FP64 node values");
+  n.add(&h->item_ctr, &ws.item_ctr, 2 * sizeof(int32_t) * Bz, "work-item counters");
   n.add(&h->part, &ws.part, sizeof(double) * nf * Bz * (size_t)std::max(h->n_items, 1), "partials");
   n.add(&h->cpart, &ws.cpart, sizeof(double) * NF_CSLICE * Bz * (size_t)combine_slices(h, B), "combine slices");
   if (merge_events(h)) n.add(&h->ev_rec, &ws.ev_rec, sizeof(double) * nf * Bz * (size_t)h->n_events, "event records");
@@ -670,7 +673,7 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
   const int setup_threads = 2 * B < h->n_cu ? 1024 : 256;
   HIPCHK(launch_setup(h->fp32, d_lambda, B, h->z_max, ws.lamc, ws.cos_tab, ws.win_tab,
                       grad ? ws.wg_tab : nullptr, (int*)ws.valid, grad ? (double*)ws.gmap : nullptr,
-                      (double*)ws.unode, h->n_z, setup_threads, st));
+                      (double*)ws.unode, h->n_z, (int32_t*)ws.item_ctr, setup_threads, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[1], st));
   SweepArgs a;
   a.samp = h->samp.p;
@@ -682,6 +685,11 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
   a.n_z = h->n_z;
   a.z_max = h->z_max;
   a.unode = (const double*)ws.unode;
+  // batched tiles take work items from a counter (dealt by a fixed stride the
+  // largest-first list loads some workgroups with the largest item of every
+  // round); one point per wavefront keeps the stride: its many small items
+  // would contend on the one counter
+  a.item_ctr = cfg.GL > 1 ? (int32_t*)ws.item_ctr : nullptr;
   a.items = h->items.as<WorkItem>();
   a.order = h->order.as<int32_t>();
   a.n_items = h->n_items;
@@ -736,6 +744,7 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
     k.gate_mode = h->gate_mode;
     k.out = (double*)ws.kde_out;
     k.evals = (unsigned long long*)ws.kde_evals;
+    k.pix_ctr = (int32_t*)ws.item_ctr + B;
     HIPCHK(launch_kde(h->fp32, k, h->n_cu, st));
     HIPCHK(launch_kde_events((const double*)ws.kde_out, split ? h->ev_part_off.as<int64_t>() : h->ev_pix_off.as<int64_t>(),
                              k.n_parts, (int)h->n_events, B,
@@ -795,7 +804,7 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
   // captured graphs hold workspace addresses: drop them all when any buffer moved
   const std::vector<const void*> sig = {h->items.p,   h->order.p,   h->ev_item_off.p, h->splits.p, h->lamc.p,
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
-                                        h->unode.p,
+                                        h->unode.p,   h->item_ctr.p,
                                         h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
                                         h->ev_rec.p,  h->kde_parts.p, h->ev_part_off.p};
   if (sig != h->ws_sig) {   // (a buffer that moved waited for the previous call first)
@@ -1162,7 +1171,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
                             &h->ln_ns,     &h->kde_parts, &h->ev_part_off, &h->ev_pix_off, &h->perm, &h->kde_order,
                             &h->items,
                             &h->order,     &h->ev_item_off, &h->splits,  &h->lamc,      &h->cos_tab, &h->win_tab,
-                            &h->wg_tab,    &h->valid,    &h->part,       &h->gmap,      &h->unode, &h->kde_out, &h->kde_ev,
+                            &h->wg_tab,    &h->valid,    &h->part,       &h->gmap,      &h->unode, &h->item_ctr, &h->kde_out, &h->kde_ev,
                             &h->kde_evals, &h->cpart,    &h->ev_rec};
     double sum = 0;
     for (const DevBuf* b : bufs) sum += (double)b->n;

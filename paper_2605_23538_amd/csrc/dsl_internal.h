@@ -118,6 +118,8 @@ struct SweepArgs {
   const double* unode;       // [B][n_z] FP64 U(z_k) = (1+z_k) I(z_k) at the table nodes (FP32 adjoint), or null
   const WorkItem* items;     // in slot order
   const int32_t* order;      // processing order of items
+  int32_t* item_ctr;         // [B] per-tile counters of handed-out items (zeroed by setup), or
+                             // null: items dealt to wavefronts by a fixed stride
   int32_t n_items;
   const void* lamc;          // LamC<T>[B]
   const void* cos_tab;       // [B][NU+1] of T2
@@ -171,7 +173,11 @@ struct KdeArgs {
   int32_t gate_mode;
   double* out;               // [B][n_parts][NF_KDE]: {R, T, S1, S2}; S1, S2 only on part 0
   unsigned long long* evals; // [0] (sample, node) kernel terms, [1] grid nodes of the launch (zeroed before it)
+  int32_t* pix_ctr;          // [B] per-tile counters of handed-out pixel batches (batched kernel;
+                             // zeroed by setup), or null: pixels dealt by a fixed stride
 };
+// Pixels the batched KDE kernel takes per counter increment.
+constexpr int KDE_PIX_BATCH = 16;
 
 struct GateSplitArgs {
   double* part;              // [B][n_items][nf]

@@ -489,277 +489,296 @@ kde_tile_kernel(KdeArgs a) {
   const T* __restrict__ los = reinterpret_cast<const T*>(a.los);
   const TabView<T> tv{cosL, winL, nullptr};
   const T inv_dz = (T)((a.n_z - 1) / a.z_max);
-  for (int64_t t = (int64_t)blockIdx.x * nwaves + wave; t < a.n_pix; t += (int64_t)gridDim.x * nwaves) {
-    const int64_t p = a.order ? (int64_t)a.order[t] : t;
-    const LamC<T>& c = lamL[lam];
-    const int64_t s0 = a.pix_off[p];
-    const int n = (int)(a.pix_off[p + 1] - s0);
-    // ---- pass A (the next record is loaded while the current one is evaluated)
-    PixAcc<false, T> pa;
-    pa.zero();
-    double sz = 0.0, szz = 0.0;
-    T zlo = (T)INFINITY, zhi = (T)-INFINITY;
-    int cin = 0;
-    if (n > 0) {
-      auto at = [&](int k) { const int i = k + sg; return s0 + (i < n ? i : n - 1); };
-      Samp<T> nxt = ld_samp<T, NS>(samp, at(0));
-      for (int k0 = 0; k0 < n; k0 += NS) {
-        const Samp<T> cur = nxt;
-        if (k0 + NS < n) nxt = ld_samp<T, NS>(samp, at(k0 + NS));
-        if (k0 + sg < n && live) {
-          int ne;
-          T lin, z;
-          eval_weight<T, GL, false, true>(cur, c, tv, lam, nullptr, 0, (T)0, ne, lin, nullptr, &z);
-          pa.template add<T>(ne, lin, nullptr);
-          if (z >= (T)0) {
-            sz += (double)z;
-            szz += (double)z * (double)z;
-            zlo = fmin(zlo, z);
-            zhi = fmax(zhi, z);
-            ++cin;
-          }
-        }
-      }
-    }
-    // sample groups of a point merged by a fixed xor tree (commutative merges:
-    // every lane of a point ends with the same bits)
-#pragma unroll
-    for (int off = GL; off < 64; off <<= 1) {
-      pa.xor_merge(off);
-      sz += __shfl_xor(sz, off);
-      szz += __shfl_xor(szz, off);
-      zlo = fmin(zlo, __shfl_xor(zlo, off));
-      zhi = fmax(zhi, __shfl_xor(zhi, off));
-      cin += __shfl_xor(cin, off);
-    }
-    const int R = pa.R;
-    bool pass;
-    if (a.gate_mode == 2) pass = live && pa.S1 > 0;
-    else pass = live && pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
-    // ---- bandwidth (Appendix D) of each point, from its nin in-support redshifts
-    const int nin = cin;
-    // z of the sample of local index k, -1 beyond the support (point of this lane)
-    auto z_of = [&](int64_t k) -> T {
-      const Samp<T> sp = samp[s0 + k];
-      const T u = fma(sp.dlc, c.H0, sp.dlc * c.H0_lo);
-      return u <= c.u_max ? z_of_u<T, GL>(u, c, tv, lam) : (T)-1;
-    };
-    auto zs = [&](int r) -> double { return (double)z_of(a.perm[s0 + r]); };   // r-th smallest in-support z
-    double h = 0.0;
-    if (pass && nin >= 2 && zlo < zhi) {
-      const double sd = sqrt(fmax(szz - sz * sz / (double)nin, 0.0) / (double)(nin - 1));
-      const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));   // n^(-1/5)
-      if (a.bandwidth == 0) {
-        h = 1.06 * sd * nf;
-      } else if (a.bandwidth == 1) {
-        auto qt = [&](double pr) {
-          const double pos = pr * (double)(nin - 1);
-          const int i0 = (int)floor(pos);
-          const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
-          const double z0 = zs(i0);
-          return z0 + (pos - (double)i0) * (zs(i1) - z0);
-        };
-        h = 0.9 * fmin(sd, (qt(0.75) - qt(0.25)) / 1.34) * nf;
-      }
-    }
-    if (a.bandwidth == 2) {
-      // biweight: median and MAD by order statistics, then the midvariance sums
-      // over the samples (sample groups merged like pass A)
-      const bool bw = pass && nin >= 2 && zlo < zhi;
-      double Q = 0.0, mad = 0.0;
-      if (bw) {
-        const int m = (nin - 1) / 2;
-        Q = 0.5 * (zs(m) + zs(nin / 2));
-        const int nA = m + 1, nB = nin - m - 1;
-        // k-th smallest deviation: A_i = Q - z_(m-i) and B_i = z_(m+1+i) - Q are
-        // both ascending; binary search on how many come from A
-        auto kth = [&](int k) -> double {
-          int lo = k + 1 - nB > 0 ? k + 1 - nB : 0;
-          int hi = k + 1 < nA ? k + 1 : nA;
-          while (lo < hi) {
-            const int i = (lo + hi) >> 1, j = k + 1 - i;
-            if (Q - zs(m - i) < zs(m + j) - Q) lo = i + 1;
-            else hi = i;
-          }
-          const int j = k + 1 - lo;
-          double v = -INFINITY;
-          if (lo > 0) v = fmax(v, Q - zs(m - lo + 1));
-          if (j > 0) v = fmax(v, zs(m + j) - Q);
-          return v;
-        };
-        mad = 0.5 * (kth((nin - 1) / 2) + kth(nin / 2));
-      }
-      double num = 0.0, den = 0.0;
-      if (bw && mad > 0.0) {
-        const double iu = 1.0 / (9.0 * mad);
-        for (int k = sg; k < n; k += NS) {
-          const T z = z_of(k);
-          if (z >= (T)0) {
-            const double d = (double)z - Q, u = d * iu, uu = u * u;
-            if (fabs(u) < 1.0) {
-              const double om = 1.0 - uu;
-              num += d * d * (om * om) * (om * om);
-              den += om * (1.0 - 5.0 * uu);
+  // Pixels in batches of KDE_PIX_BATCH, batch b holding the b-th pixel of each
+  // of KDE_PIX_BATCH equal strata of the largest-first order (so no batch
+  // gathers the largest pixels): each wavefront's first batch by a fixed
+  // stride, the rest from the tile's counter (by a stride, the largest-first
+  // order would give the same workgroups the largest pixels of every round);
+  // every pixel writes its own record, so the results do not depend on which
+  // wavefront took it.
+  constexpr int PB = KDE_PIX_BATCH;
+  const int64_t n_bat = (a.n_pix + PB - 1) / PB;
+  const int64_t n_first = (int64_t)gridDim.x * nwaves;
+  int32_t* const ctr = a.pix_ctr && n_first < n_bat ? a.pix_ctr + tile : nullptr;
+  auto next_batch = [&](int64_t bt) -> int64_t {
+    if (!ctr) return bt + n_first;
+    int v = 0;
+    if (lane == 0) v = atomicAdd(ctr, 1);
+    return n_first + __builtin_amdgcn_readfirstlane(v);
+  };
+  for (int64_t bt = (int64_t)blockIdx.x * nwaves + wave; bt < n_bat; bt = next_batch(bt)) {
+    for (int64_t t = bt; t < a.n_pix; t += n_bat) {
+      const int64_t p = a.order ? (int64_t)a.order[t] : t;
+      const LamC<T>& c = lamL[lam];
+      const int64_t s0 = a.pix_off[p];
+      const int n = (int)(a.pix_off[p + 1] - s0);
+      // ---- pass A (the next record is loaded while the current one is evaluated)
+      PixAcc<false, T> pa;
+      pa.zero();
+      double sz = 0.0, szz = 0.0;
+      T zlo = (T)INFINITY, zhi = (T)-INFINITY;
+      int cin = 0;
+      if (n > 0) {
+        auto at = [&](int k) { const int i = k + sg; return s0 + (i < n ? i : n - 1); };
+        Samp<T> nxt = ld_samp<T, NS>(samp, at(0));
+        for (int k0 = 0; k0 < n; k0 += NS) {
+          const Samp<T> cur = nxt;
+          if (k0 + NS < n) nxt = ld_samp<T, NS>(samp, at(k0 + NS));
+          if (k0 + sg < n && live) {
+            int ne;
+            T lin, z;
+            eval_weight<T, GL, false, true>(cur, c, tv, lam, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+            pa.template add<T>(ne, lin, nullptr);
+            if (z >= (T)0) {
+              sz += (double)z;
+              szz += (double)z * (double)z;
+              zlo = fmin(zlo, z);
+              zhi = fmax(zhi, z);
+              ++cin;
             }
           }
         }
       }
-#pragma unroll
+      // sample groups of a point merged by a fixed xor tree (commutative merges:
+      // every lane of a point ends with the same bits)
+  #pragma unroll
       for (int off = GL; off < 64; off <<= 1) {
-        num += __shfl_xor(num, off);
-        den += __shfl_xor(den, off);
+        pa.xor_merge(off);
+        sz += __shfl_xor(sz, off);
+        szz += __shfl_xor(szz, off);
+        zlo = fmin(zlo, __shfl_xor(zlo, off));
+        zhi = fmax(zhi, __shfl_xor(zhi, off));
+        cin += __shfl_xor(cin, off);
       }
-      if (bw && mad > 0.0) {
-        const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));
-        const double bm = (double)nin * num / (den * den);
-        h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
-      }
-    }
-    const bool kde_row = pass && h > 0.0 && isfinite(h);
-    if (sg == 0 && act) {
-      // (T of a passing pair is written by its row in the grid stage)
-      double* out = a.out + ((size_t)(tile * GL + lam) * a.n_pix + p) * NF_KDE;
-      out[0] = pass ? (double)R : 0.0;
-      if (!pass) out[1] = 0.0;
-      out[2] = pass ? pa.S1 : 0.0;
-      out[3] = pass ? pa.S2 : 0.0;
-    }
-    // ---- grid stage: the passing points, four per round, one 16-lane row each
-    const unsigned long long pm = __ballot(sg == 0 && pass);
-    const int np = __popcll(pm);
-    const T* __restrict__ row = los + (size_t)a.pix_row[p] * a.n_z;
-    for (int r0 = 0; r0 < np; r0 += 4) {
-      const int kq = r0 + q;
-      const bool ract = kq < np;
-      const int src = ract ? nth_set_bit(pm, kq) : 0;   // a lane with sg = 0: its point is lam = src
-      const int lp = src;
-      const int Rp = __shfl(R, src);
-      const double hp = __shfl(h, src);
-      const T zlop = __shfl(zlo, src), zhip = __shfl(zhi, src);
-      const bool krow = __shfl((int)kde_row, src) != 0;
-      const LamC<T>& cp = lamL[lp];
-      // the lane's redshift and scaled weight of sample c0 + kl (samples below lim)
-      auto z_w = [&](int c0, int lim, T& z, T& w) {
-        const int k = c0 + kl;
-        z = (T)-1;
-        w = (T)0;
-        if (k < lim && ract) {
-          int ne;
-          T lin;
-          eval_weight<T, GL, false, true>(samp[s0 + k], cp, tv, lp, nullptr, 0, (T)0, ne, lin, nullptr, &z);
-          if (z >= (T)0 && lin > (T)0) w = ldexp(lin, ne - Rp);
-        }
+      const int R = pa.R;
+      bool pass;
+      if (a.gate_mode == 2) pass = live && pa.S1 > 0;
+      else pass = live && pa.S2 > 0 && pa.S1 * pa.S1 >= a.neff_min * pa.S2;
+      // ---- bandwidth (Appendix D) of each point, from its nin in-support redshifts
+      const int nin = cin;
+      // z of the sample of local index k, -1 beyond the support (point of this lane)
+      auto z_of = [&](int64_t k) -> T {
+        const Samp<T> sp = samp[s0 + k];
+        const T u = fma(sp.dlc, c.H0, sp.dlc * c.H0_lo);
+        return u <= c.u_max ? z_of_u<T, GL>(u, c, tv, lam) : (T)-1;
       };
-      double Tt = 0.0;
-      if (ract && !krow) {
-        // zero bandwidth: point masses at the samples
-        for (int c0 = 0; c0 < n; c0 += 16) {
-          T z, w;
-          z_w(c0, n, z, w);
-          if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(cp, z));
+      auto zs = [&](int r) -> double { return (double)z_of(a.perm[s0 + r]); };   // r-th smallest in-support z
+      double h = 0.0;
+      if (pass && nin >= 2 && zlo < zhi) {
+        const double sd = sqrt(fmax(szz - sz * sz / (double)nin, 0.0) / (double)(nin - 1));
+        const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));   // n^(-1/5)
+        if (a.bandwidth == 0) {
+          h = 1.06 * sd * nf;
+        } else if (a.bandwidth == 1) {
+          auto qt = [&](double pr) {
+            const double pos = pr * (double)(nin - 1);
+            const int i0 = (int)floor(pos);
+            const int i1 = i0 + 1 < nin ? i0 + 1 : nin - 1;
+            const double z0 = zs(i0);
+            return z0 + (pos - (double)i0) * (zs(i1) - z0);
+          };
+          h = 0.9 * fmin(sd, (qt(0.75) - qt(0.25)) / 1.34) * nf;
         }
-        Tt = row_reduce(Tt, [](double x, double y) { return x + y; });
-      } else if (ract) {
-        const double ga = fmax(0.0, (double)zlop - a.tau * hp);
-        const double gb = fmin(a.z_max, (double)zhip + a.tau * hp);
-        const double dz = (gb - ga) / (double)(a.n_grid - 1);
-        // coordinates scaled by sqrt(log2(e)/2)/h and measured from ga, so each
-        // term is exp2(-(x_g - x_k)^2); S is the node spacing in these units;
-        // the node-to-node ratio recurrence as in the row kernel
-        const T invh = (T)(sqrt(0.5 * LOG2E) / hp);
-        const T S = (T)(dz * (sqrt(0.5 * LOG2E) / hp));
-        const bool rec = S <= (T)0.25 && (T)2 * S * S * (T)(a.n_grid - 1) <= (T)64;
-        const T ra = -(cp.gm3 + (T)2), rb = cp.gk - (cp.gm3 + (T)2), rc = -cp.gk * cp.Lp;
-        const unsigned nz2 = (unsigned)(a.n_z - 2);
-        if (kl == 0 && a.evals) atomicAdd(&work[1], (unsigned long long)a.n_grid);
-        for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
-          T vg[NB];
-          const int gl = g0 + NB * kl;
-          double zd = ga + (double)gl * dz;
-          const T cw = (T)a.n_grid - (T)0.5 - (T)gl;
-          const T x0l = (T)((double)gl * dz) * invh;
-          const T r0 = Mth<T>::exp2(-(S * S));
-          const T r2 = r0 * r0;
-          T Ci = (T)1, ri = r0;
-          constexpr int LB = 8;
-#pragma unroll
-          for (int i0 = 0; i0 < NB; i0 += LB) {
-            T lp0[LB], lp1[LB];
-            T zgv[LB], fz[LB];
-#pragma unroll
-            for (int i = 0; i < LB; ++i) {
-              const T zg = (T)fmin(zd, a.z_max);
-              zd += dz;
-              const T x = zg * inv_dz;
-              unsigned k = (unsigned)x;
-              k = k < nz2 ? k : nz2;
-              zgv[i] = zg;
-              fz[i] = x - (T)k;
-              los_pair(row, k, lp0[i], lp1[i]);
+      }
+      if (a.bandwidth == 2) {
+        // biweight: median and MAD by order statistics, then the midvariance sums
+        // over the samples (sample groups merged like pass A)
+        const bool bw = pass && nin >= 2 && zlo < zhi;
+        double Q = 0.0, mad = 0.0;
+        if (bw) {
+          const int m = (nin - 1) / 2;
+          Q = 0.5 * (zs(m) + zs(nin / 2));
+          const int nA = m + 1, nB = nin - m - 1;
+          // k-th smallest deviation: A_i = Q - z_(m-i) and B_i = z_(m+1+i) - Q are
+          // both ascending; binary search on how many come from A
+          auto kth = [&](int k) -> double {
+            int lo = k + 1 - nB > 0 ? k + 1 - nB : 0;
+            int hi = k + 1 < nA ? k + 1 : nA;
+            while (lo < hi) {
+              const int i = (lo + hi) >> 1, j = k + 1 - i;
+              if (Q - zs(m - i) < zs(m + j) - Q) lo = i + 1;
+              else hi = i;
             }
-#pragma unroll
-            for (int i = 0; i < LB; ++i) {
-              const int ii = i0 + i;
-              const T zg = zgv[i];
-              const T cg = fmin(fmax(cw - (T)ii, (T)0), (T)1);
-              const T L = Mth<T>::log2((T)1 + zg);
-              const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
-              vg[ii] = cg * rate * (lp0[i] + fz[i] * (lp1[i] - lp0[i])) * (rec ? Ci : (T)1);
-              Ci *= ri;
-              ri *= r2;
+            const int j = k + 1 - lo;
+            double v = -INFINITY;
+            if (lo > 0) v = fmax(v, Q - zs(m - lo + 1));
+            if (j > 0) v = fmax(v, zs(m + j) - Q);
+            return v;
+          };
+          mad = 0.5 * (kth((nin - 1) / 2) + kth(nin / 2));
+        }
+        double num = 0.0, den = 0.0;
+        if (bw && mad > 0.0) {
+          const double iu = 1.0 / (9.0 * mad);
+          for (int k = sg; k < n; k += NS) {
+            const T z = z_of(k);
+            if (z >= (T)0) {
+              const double d = (double)z - Q, u = d * iu, uu = u * u;
+              if (fabs(u) < 1.0) {
+                const double om = 1.0 - uu;
+                num += d * d * (om * om) * (om * om);
+                den += om * (1.0 - 5.0 * uu);
+              }
             }
           }
-          if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
-          const T A = Mth<T>::exp2((T)-2 * S * x0l);
+        }
+  #pragma unroll
+        for (int off = GL; off < 64; off <<= 1) {
+          num += __shfl_xor(num, off);
+          den += __shfl_xor(den, off);
+        }
+        if (bw && mad > 0.0) {
+          const double nf = (double)Mth<T>::exp2((T)-0.2 * Mth<T>::log2((T)nin));
+          const double bm = (double)nin * num / (den * den);
+          h = bm > 0.0 ? 1.06 * sqrt(bm) * nf : 0.0;
+        }
+      }
+      const bool kde_row = pass && h > 0.0 && isfinite(h);
+      if (sg == 0 && act) {
+        // (T of a passing pair is written by its row in the grid stage)
+        double* out = a.out + ((size_t)(tile * GL + lam) * a.n_pix + p) * NF_KDE;
+        out[0] = pass ? (double)R : 0.0;
+        if (!pass) out[1] = 0.0;
+        out[2] = pass ? pa.S1 : 0.0;
+        out[3] = pass ? pa.S2 : 0.0;
+      }
+      // ---- grid stage: the passing points, four per round, one 16-lane row each
+      const unsigned long long pm = __ballot(sg == 0 && pass);
+      const int np = __popcll(pm);
+      const T* __restrict__ row = los + (size_t)a.pix_row[p] * a.n_z;
+      for (int r0 = 0; r0 < np; r0 += 4) {
+        const int kq = r0 + q;
+        const bool ract = kq < np;
+        const int src = ract ? nth_set_bit(pm, kq) : 0;   // a lane with sg = 0: its point is lam = src
+        const int lp = src;
+        const int Rp = __shfl(R, src);
+        const double hp = __shfl(h, src);
+        const T zlop = __shfl(zlo, src), zhip = __shfl(zhi, src);
+        const bool krow = __shfl((int)kde_row, src) != 0;
+        const LamC<T>& cp = lamL[lp];
+        // the lane's redshift and scaled weight of sample c0 + kl (samples below lim)
+        auto z_w = [&](int c0, int lim, T& z, T& w) {
+          const int k = c0 + kl;
+          z = (T)-1;
+          w = (T)0;
+          if (k < lim && ract) {
+            int ne;
+            T lin;
+            eval_weight<T, GL, false, true>(samp[s0 + k], cp, tv, lp, nullptr, 0, (T)0, ne, lin, nullptr, &z);
+            if (z >= (T)0 && lin > (T)0) w = ldexp(lin, ne - Rp);
+          }
+        };
+        double Tt = 0.0;
+        if (ract && !krow) {
+          // zero bandwidth: point masses at the samples
           for (int c0 = 0; c0 < n; c0 += 16) {
             T z, w;
             z_w(c0, n, z, w);
-            const T zr = (z - (T)ga) * invh;
-            const T Bk = Mth<T>::exp2((T)2 * S * zr);
-            const int cnt = n - c0 < 16 ? n - c0 : 16;
-            if (g0 == 0) {
-              const unsigned long long m = __ballot(w > (T)0);
-              if (kl == 0 && a.evals)
-                atomicAdd(&work[0], (unsigned long long)__popcll((m >> (16 * q)) & 0xffffull) * a.n_grid);
-            }
-            T accf[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) accf[i] = (T)0;
-            int j = 0;
-            if (rec) {
-              do {
-                const T wj = __shfl(w, j, 16);
-                const T zj = __shfl(zr, j, 16);
-                const T P = A * __shfl(Bk, j, 16);
-                const T x0 = x0l - zj;
-                T u = wj * Mth<T>::exp2(-(x0 * x0));
-                accf[0] += u;
-#pragma unroll
-                for (int i = 1; i < NB; ++i) {
-                  u *= P;
-                  accf[i] += u;
-                }
-              } while (++j < cnt);
-            } else {
-              do {
-                const T wj = __shfl(w, j, 16);
-                const T zj = __shfl(zr, j, 16);
-#pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                  const T xx = fma((T)i, S, x0l) - zj;
-                  accf[i] = fma(wj, Mth<T>::exp2(-(xx * xx)), accf[i]);
-                }
-              } while (++j < cnt);
-            }
-            T part = (T)0;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) part = fma(vg[i], accf[i], part);
-            Tt += (double)part;
+            if (w > (T)0) Tt += (double)w * (double)(los_at<T>(row, a.n_z, inv_dz, z) * rate_at<T>(cp, z));
           }
+          Tt = row_reduce(Tt, [](double x, double y) { return x + y; });
+        } else if (ract) {
+          const double ga = fmax(0.0, (double)zlop - a.tau * hp);
+          const double gb = fmin(a.z_max, (double)zhip + a.tau * hp);
+          const double dz = (gb - ga) / (double)(a.n_grid - 1);
+          // coordinates scaled by sqrt(log2(e)/2)/h and measured from ga, so each
+          // term is exp2(-(x_g - x_k)^2); S is the node spacing in these units;
+          // the node-to-node ratio recurrence as in the row kernel
+          const T invh = (T)(sqrt(0.5 * LOG2E) / hp);
+          const T S = (T)(dz * (sqrt(0.5 * LOG2E) / hp));
+          const bool rec = S <= (T)0.25 && (T)2 * S * S * (T)(a.n_grid - 1) <= (T)64;
+          const T ra = -(cp.gm3 + (T)2), rb = cp.gk - (cp.gm3 + (T)2), rc = -cp.gk * cp.Lp;
+          const unsigned nz2 = (unsigned)(a.n_z - 2);
+          if (kl == 0 && a.evals) atomicAdd(&work[1], (unsigned long long)a.n_grid);
+          for (int g0 = 0; g0 < a.n_grid; g0 += 16 * NB) {
+            T vg[NB];
+            const int gl = g0 + NB * kl;
+            double zd = ga + (double)gl * dz;
+            const T cw = (T)a.n_grid - (T)0.5 - (T)gl;
+            const T x0l = (T)((double)gl * dz) * invh;
+            const T r0 = Mth<T>::exp2(-(S * S));
+            const T r2 = r0 * r0;
+            T Ci = (T)1, ri = r0;
+            constexpr int LB = 8;
+  #pragma unroll
+            for (int i0 = 0; i0 < NB; i0 += LB) {
+              T lp0[LB], lp1[LB];
+              T zgv[LB], fz[LB];
+  #pragma unroll
+              for (int i = 0; i < LB; ++i) {
+                const T zg = (T)fmin(zd, a.z_max);
+                zd += dz;
+                const T x = zg * inv_dz;
+                unsigned k = (unsigned)x;
+                k = k < nz2 ? k : nz2;
+                zgv[i] = zg;
+                fz[i] = x - (T)k;
+                los_pair(row, k, lp0[i], lp1[i]);
+              }
+  #pragma unroll
+              for (int i = 0; i < LB; ++i) {
+                const int ii = i0 + i;
+                const T zg = zgv[i];
+                const T cg = fmin(fmax(cw - (T)ii, (T)0), (T)1);
+                const T L = Mth<T>::log2((T)1 + zg);
+                const T rate = Mth<T>::rcp(Mth<T>::exp2(ra * L) + Mth<T>::exp2(fma(rb, L, rc)));
+                vg[ii] = cg * rate * (lp0[i] + fz[i] * (lp1[i] - lp0[i])) * (rec ? Ci : (T)1);
+                Ci *= ri;
+                ri *= r2;
+              }
+            }
+            if (g0 == 0 && kl == 0) vg[0] *= (T)0.5;
+            const T A = Mth<T>::exp2((T)-2 * S * x0l);
+            for (int c0 = 0; c0 < n; c0 += 16) {
+              T z, w;
+              z_w(c0, n, z, w);
+              const T zr = (z - (T)ga) * invh;
+              const T Bk = Mth<T>::exp2((T)2 * S * zr);
+              const int cnt = n - c0 < 16 ? n - c0 : 16;
+              if (g0 == 0) {
+                const unsigned long long m = __ballot(w > (T)0);
+                if (kl == 0 && a.evals)
+                  atomicAdd(&work[0], (unsigned long long)__popcll((m >> (16 * q)) & 0xffffull) * a.n_grid);
+              }
+              T accf[NB];
+  #pragma unroll
+              for (int i = 0; i < NB; ++i) accf[i] = (T)0;
+              int j = 0;
+              if (rec) {
+                do {
+                  const T wj = __shfl(w, j, 16);
+                  const T zj = __shfl(zr, j, 16);
+                  const T P = A * __shfl(Bk, j, 16);
+                  const T x0 = x0l - zj;
+                  T u = wj * Mth<T>::exp2(-(x0 * x0));
+                  accf[0] += u;
+  #pragma unroll
+                  for (int i = 1; i < NB; ++i) {
+                    u *= P;
+                    accf[i] += u;
+                  }
+                } while (++j < cnt);
+              } else {
+                do {
+                  const T wj = __shfl(w, j, 16);
+                  const T zj = __shfl(zr, j, 16);
+  #pragma unroll
+                  for (int i = 0; i < NB; ++i) {
+                    const T xx = fma((T)i, S, x0l) - zj;
+                    accf[i] = fma(wj, Mth<T>::exp2(-(xx * xx)), accf[i]);
+                  }
+                } while (++j < cnt);
+              }
+              T part = (T)0;
+  #pragma unroll
+              for (int i = 0; i < NB; ++i) part = fma(vg[i], accf[i], part);
+              Tt += (double)part;
+            }
+          }
+          Tt = row_reduce(Tt, [](double x, double y) { return x + y; }) * dz / (hp * 2.5066282746310002);
         }
-        Tt = row_reduce(Tt, [](double x, double y) { return x + y; }) * dz / (hp * 2.5066282746310002);
+        if (ract && kl == 0) a.out[((size_t)(tile * GL + lp) * a.n_pix + p) * NF_KDE + 1] = Tt;
       }
-      if (ract && kl == 0) a.out[((size_t)(tile * GL + lp) * a.n_pix + p) * NF_KDE + 1] = Tt;
     }
   }
   __syncthreads();

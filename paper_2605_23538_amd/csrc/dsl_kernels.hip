@@ -88,7 +88,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
                                                     typename V2<T>::t* __restrict__ win_tab,
                                                     typename V2<T>::t* __restrict__ win_grad_tab,
                                                     int* __restrict__ valid_out, double* __restrict__ gmap,
-                                                    double* __restrict__ unode, int n_z) {
+                                                    double* __restrict__ unode, int n_z,
+                                                    int32_t* __restrict__ item_ctr) {
   using T2 = typename V2<T>::t;
   constexpr int NU = Tab<T>::NU, NW = Tab<T>::NW, NWG = Tab<T>::NWG;
   const int b = blockIdx.x;
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
   // two workgroups per point: part 0 the cosmology and rate, part 1 the mass model
   const int part = blockIdx.y;
   LamC<T>& c = lamc[b];
+  // (the sweep's and the KDE kernel's tiles number at most B each)
+  if (item_ctr && part == 0 && tid == 0) item_ctr[b] = item_ctr[B + b] = 0;
   if (part == 0) {
     // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
     constexpr int KZ = KZ_I;
@@ -564,7 +567,20 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, SweepMaxThreads<T, GL, 
   const double* __restrict__ un = (a.unode && !SPEC && active) ? a.unode + (size_t)b * a.n_z : nullptr;
   T g[GRAD ? 16 : 1];
 
-  for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it += gridDim.x * nwaves) {
+  // Work items: each wavefront's first by a fixed stride, the rest from the
+  // tile's counter (the list runs largest first, so a fixed stride would give
+  // the same workgroups the largest item of every round); every item writes
+  // its own slot, so the results do not depend on which wavefront took it.
+  // (a list the first round covers needs no counter)
+  const int n_first = gridDim.x * nwaves;
+  int32_t* const ctr = a.item_ctr && a.n_items > n_first ? a.item_ctr + tile : nullptr;
+  auto next_item = [&](int it) -> int {
+    if (!ctr) return it + n_first;
+    int v = 0;
+    if (lane == 0) v = atomicAdd(ctr, 1);
+    return n_first + __builtin_amdgcn_readfirstlane(v);
+  };
+  for (int it = blockIdx.x * nwaves + wave; it < a.n_items; it = next_item(it)) {
     const WorkItem w = a.items[a.order[it]];
     if (a.skip_events && w.event >= 0) continue;
     ItemAcc<GRAD, T> chunk;
@@ -1085,14 +1101,14 @@ hipError_t launch_pack(int fp32, const double* m1, const double* m2, const doubl
 // threads: per workgroup, 256 ... SETUP_THREADS (the loops stride by the block size).
 hipError_t launch_setup(int fp32, const double* lam, int B, double z_max, void* lamc, void* cos_tab,
                         void* win_tab, void* win_grad_tab, int* valid, double* gmap, double* unode, int n_z,
-                        int threads, hipStream_t st) {
+                        int32_t* item_ctr, int threads, hipStream_t st) {
   if (threads < 256 || threads > SETUP_THREADS || threads % 64) return hipErrorInvalidValue;
   if (fp32)
     setup_kernel<float><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<float>*)lamc, (float2*)cos_tab,
-                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap, unode, n_z);
+                                      (float2*)win_tab, (float2*)win_grad_tab, valid, gmap, unode, n_z, item_ctr);
   else
     setup_kernel<double><<<dim3(B, 2), threads, 0, st>>>(lam, B, z_max, (LamC<double>*)lamc, (double2*)cos_tab,
-                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap, unode, n_z);
+                                       (double2*)win_tab, (double2*)win_grad_tab, valid, gmap, unode, n_z, item_ctr);
   return hipGetLastError();
 }
 
