@@ -345,18 +345,21 @@ __device__ __forceinline__ void eval_weight(const Samp<T>& sp, const LamC<T>& c,
   }
 }
 
-// Sample record loads: with one sample per wavefront (NS == 1) the address is
-// uniform, so it goes through the scalar cache (constant address space).
+// A value that is the same on every lane, taken as a scalar (the compiler then
+// keeps it, and what is computed from it, in scalar registers).
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+// Sample record loads: with one sample per wavefront (NS == 1) the index is
+// uniform, so the address is a scalar base (the record still arrives in
+// vector registers, through the vector cache).
 template <typename T, int NS>
 __device__ __forceinline__ Samp<T> ld_samp(const Samp<T>* __restrict__ p, int64_t i) {
-  if constexpr (NS == 1) {
-    const int lo = __builtin_amdgcn_readfirstlane((int)(i & 0xffffffff));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(i >> 32));
-    const int64_t u = ((int64_t)hi << 32) | (uint32_t)lo;
-    return p[u];
-  } else {
-    return p[i];
-  }
+  if constexpr (NS == 1) return p[uniform64(i)];
+  else return p[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -440,7 +440,7 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long m, int k) {
 // Batched KDE numerator (four or more points): one wavefront per (pixel, tile
 // of GL points), pixels largest first.  Pass A in the sweep's layout: GL points
 // x 64/GL sample groups per wavefront (GL = 64: one lane per point, each sample
-// record read once for the tile through the scalar cache); Eq. (7) weights
+// record loaded once for the tile from a uniform address); Eq. (7) weights
 // without prior and rate, Eq. (8) sums, in-support redshift moments and range,
 // the gate and the bandwidth of every point at once.  Grid stage: the points of
 // the pixel that pass are packed into the wavefront's four 16-lane rows, four
@@ -508,10 +508,12 @@ kde_tile_kernel(KdeArgs a) {
   };
   for (int64_t bt = (int64_t)blockIdx.x * nwaves + wave; bt < n_bat; bt = next_batch(bt)) {
     for (int64_t t = bt; t < a.n_pix; t += n_bat) {
-      const int64_t p = a.order ? (int64_t)a.order[t] : t;
+      // (pixel and bounds are the same on every lane: scalars keep pass A's
+      // loop counter and record addresses off the vector unit)
+      const int64_t p = uniform64(a.order ? (int64_t)a.order[t] : t);
       const LamC<T>& c = lamL[lam];
-      const int64_t s0 = a.pix_off[p];
-      const int n = (int)(a.pix_off[p + 1] - s0);
+      const int64_t s0 = uniform64(a.pix_off[p]);
+      const int n = (int)(uniform64(a.pix_off[p + 1]) - s0);
       // ---- pass A (the next record is loaded while the current one is evaluated)
       PixAcc<false, T> pa;
       pa.zero();

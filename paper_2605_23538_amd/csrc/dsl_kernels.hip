@@ -475,28 +475,45 @@ struct ItemAcc {
 };
 
 // One run of samples [s0, s1) accumulated into acc; the next record is
-// loaded while the current one is evaluated.
+// loaded while the current one is evaluated.  The bounds are the same on
+// every lane: as scalars they keep the loop's counter and the record
+// addresses off the vector unit.
 template <typename T, int GL, bool GRAD, bool SPEC, typename AccT>
 __device__ __forceinline__ void sweep_run(const Samp<T>* __restrict__ base, int64_t s0, int64_t s1, int sg,
                                           bool live, const LamC<T>& c, const TabView<T>& tv, int lam,
                                           const T* __restrict__ tab, int n_z, T inv_dz, AccT& acc,
                                           T* g, const double* __restrict__ unode) {
   constexpr int NS = 64 / GL;
+  s0 = uniform64(s0);
+  s1 = uniform64(s1);
   if (s1 <= s0) return;
+  if constexpr (NS == 1) {
+    // one sample per wavefront (a 32-bit count from the run's first record:
+    // the scalar unit has no signed 64-bit compare)
+    const Samp<T>* __restrict__ rp = base + s0;
+    const int n = (int)(s1 - s0);
+    Samp<T> nxt = ld_samp<T, 1>(rp, 0);
+    for (int k = 0; k < n; ++k) {
+      const Samp<T> cur = nxt;
+      if (k + 1 < n) nxt = ld_samp<T, 1>(rp, k + 1);
+      if (live) {
+        int nw;
+        T lin;
+        eval_weight<T, GL, GRAD, false, SPEC>(cur, c, tv, lam, tab, n_z, inv_dz, nw, lin, g, nullptr, unode);
+        acc.template add<T>(nw, lin, g);
+      }
+    }
+    return;
+  }
   // indices are clamped into the run; with several samples per wavefront two
   // records are in flight (one point per lane leaves little work to hide a load)
   auto at = [&](int64_t sb) { const int64_t i = sb + sg; return i < s1 ? i : s1 - 1; };
   Samp<T> nxt = ld_samp<T, NS>(base, at(s0));
-  Samp<T> nxt2;
-  if constexpr (NS > 1) nxt2 = ld_samp<T, NS>(base, at(s0 + NS));
+  Samp<T> nxt2 = ld_samp<T, NS>(base, at(s0 + NS));
   for (int64_t sb = s0; sb < s1; sb += NS) {
     const Samp<T> cur = nxt;
-    if constexpr (NS > 1) {
-      nxt = nxt2;
-      if (sb + 2 * NS < s1) nxt2 = ld_samp<T, NS>(base, at(sb + 2 * NS));
-    } else if (sb + NS < s1) {
-      nxt = ld_samp<T, NS>(base, at(sb + NS));
-    }
+    nxt = nxt2;
+    if (sb + 2 * NS < s1) nxt2 = ld_samp<T, NS>(base, at(sb + 2 * NS));
     if (sb + sg < s1 && live) {
       int n;
       T lin;
