@@ -126,8 +126,7 @@ struct dsl_handle {
   DevBuf items, order, ev_item_off, splits;
   int n_items = 0, inj_slot0 = 0, inj_slot1 = 0, n_split = 0;
   // workspace
-  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, unode, item_ctr, kde_out, kde_ev, kde_evals, cpart,
-      ev_rec;
+  DevBuf lamc, cos_tab, win_tab, wg_tab, valid, part, gmap, unode, item_ctr, kde_out, kde_ev, kde_evals, cpart;
   // options
   double neff_min = 2.0;
   int gate_mode = 0;
@@ -585,7 +584,7 @@ int build_kde_parts(dsl_handle* h, int64_t P) {
 }
 
 // Events spanning many work items (the monte-carlo numerator) are merged by one
-// wavefront each before the combine, instead of one thread walking the items.
+// wavefront of the combine each, instead of one thread walking the items.
 bool merge_events(const dsl_handle* h) {
   return h->numerator == 0 && h->n_events > 0 && h->inj_slot0 >= 16 * h->n_events;
 }
@@ -600,10 +599,9 @@ struct Ws {
   void* valid = nullptr;
   void* gmap = nullptr;
   void* unode = nullptr;   // FP64 (1+z) I(z) at the table nodes (FP32 adjoint)
-  void* item_ctr = nullptr;   // per-tile work-item counters of the sweep
+  void* item_ctr = nullptr;   // per-tile work-item counters, per-point slice counters
   void* part = nullptr;
   void* cpart = nullptr;
-  void* ev_rec = nullptr;
   void* kde_out = nullptr;
   void* kde_ev = nullptr;
   void* kde_evals = nullptr;
@@ -641,10 +639,9 @@ WsNeeds workspace_needs(dsl_handle* h, int B, bool grad, Ws& ws) {
   n.add(&h->valid, &ws.valid, sizeof(int) * Bz, "valid");
   n.add(&h->gmap, &ws.gmap, sizeof(double) * N_GMAP * Bz, "gmap");
   if (h->fp32 && grad) n.add(&h->unode, &ws.unode, sizeof(double) * (size_t)h->n_z * Bz, "FP64 node values");
-  n.add(&h->item_ctr, &ws.item_ctr, 2 * sizeof(int32_t) * Bz, "work-item counters");
+  n.add(&h->item_ctr, &ws.item_ctr, 3 * sizeof(int32_t) * Bz, "work-item and slice counters");
   n.add(&h->part, &ws.part, sizeof(double) * nf * Bz * (size_t)std::max(h->n_items, 1), "partials");
   n.add(&h->cpart, &ws.cpart, sizeof(double) * NF_CSLICE * Bz * (size_t)combine_slices(h, B), "combine slices");
-  if (merge_events(h)) n.add(&h->ev_rec, &ws.ev_rec, sizeof(double) * nf * Bz * (size_t)h->n_events, "event records");
   if (h->numerator == 1) {
     const int64_t units = std::max<int64_t>(kde_part_size(h, B) ? h->n_kde_parts : h->n_pix, 1);
     n.add(&h->kde_out, &ws.kde_out, sizeof(double) * NF_KDE * Bz * (size_t)units, "KDE pixel terms");
@@ -790,9 +787,10 @@ int enqueue(dsl_handle* h, const Ws& ws, const double* d_lambda, int B, bool gra
   c.grad = o.grad;
   c.gmap = (const double*)ws.gmap;
   c.kde = h->numerator == 1 ? (const double*)ws.kde_ev : nullptr;
-  c.ev_rec = merge_events(h) ? (double*)ws.ev_rec : nullptr;
+  c.wave_events = merge_events(h) ? 1 : 0;
   c.n_slices = combine_slices(h, B);
   c.cpart = (double*)ws.cpart;
+  c.slice_ctr = (int32_t*)ws.item_ctr + 2 * B;
   HIPCHK(launch_combine(grad, c, st));
   if (timed) HIPCHK(hipEventRecord(h->ev[3], st));
   return DSL_OK;
@@ -821,7 +819,7 @@ int run(dsl_handle* h, const double* d_lambda, int B, bool grad, const CallOut& 
                                         h->cos_tab.p, h->win_tab.p, h->wg_tab.p,      h->valid.p,  h->gmap.p,
                                         h->unode.p,   h->item_ctr.p,
                                         h->part.p,    h->kde_out.p, h->kde_ev.p,      h->kde_evals.p, h->cpart.p,
-                                        h->ev_rec.p,  h->kde_parts.p, h->ev_part_off.p};
+                                        h->kde_parts.p, h->ev_part_off.p};
   if (sig != h->ws_sig) {   // (a buffer that moved waited for the previous call first)
     drop_graphs(h);
     h->ws_sig = sig;
@@ -1188,7 +1186,7 @@ int dsl_get_info(dsl_handle* h, const char* key, double* v) {
                             &h->items,
                             &h->order,     &h->ev_item_off, &h->splits,  &h->lamc,      &h->cos_tab, &h->win_tab,
                             &h->wg_tab,    &h->valid,    &h->part,       &h->gmap,      &h->unode, &h->item_ctr, &h->kde_out, &h->kde_ev,
-                            &h->kde_evals, &h->cpart,    &h->ev_rec};
+                            &h->kde_evals, &h->cpart};
     double sum = 0;
     for (const DevBuf* b : bufs) sum += (double)b->n;
     *v = sum;

@@ -215,9 +215,11 @@ struct CombineArgs {
   double* grad;                 // [B][16] or null
   const double* gmap;           // [B][N_GMAP] (adjoint only)
   const double* kde;            // [B][n_events][NF_KDE] event records (KDE numerator) or null
-  double* ev_rec;               // [B][n_events][nf] per-event merged item records, or null
+  int32_t wave_events;          // 1: one wavefront merges an event's items (events of many items)
   int32_t n_slices;             // workgroups per point (events and injection slots strided over them)
   double* cpart;                // [B][n_slices][NF_CSLICE] slice records when n_slices > 1
+  int32_t* slice_ctr;           // [B] finished slices per point (zeroed by setup): the last one merges
+                                // the slice records; null: a separate merge launch does
 };
 
 }  // namespace dsl

@@ -112,8 +112,9 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(const double* __re
   // two workgroups per point: part 0 the cosmology and rate, part 1 the mass model
   const int part = blockIdx.y;
   LamC<T>& c = lamc[b];
-  // (the sweep's and the KDE kernel's tiles number at most B each)
-  if (item_ctr && part == 0 && tid == 0) item_ctr[b] = item_ctr[B + b] = 0;
+  // (the sweep's and the KDE kernel's tiles number at most B each; then the
+  // combine's per-point slice counters)
+  if (item_ctr && part == 0 && tid == 0) item_ctr[b] = item_ctr[B + b] = item_ctr[2 * B + b] = 0;
   if (part == 0) {
     // --- I(z) on KZ uniform panels (8-point Gauss-Legendre each), prefix-summed.
     constexpr int KZ = KZ_I;
@@ -791,20 +792,16 @@ __device__ void combine_finish(const CombineArgs& a, int b, double acc, double n
   }
 }
 
-// Per (event, point): merge the event's item records with one wavefront (lanes
-// stride over the items, then a fixed xor butterfly whose merges are exact
-// power-of-two rescalings and commutative sums, so every lane ends with the
-// same bits); the result, in the item layout, goes to ev_rec.  Used when events
-// span many items, where one thread per event would walk them serially.
+// Merge of one event's item records by one wavefront (lanes stride over the
+// items, then a fixed xor butterfly whose merges are exact power-of-two
+// rescalings and commutative sums, so every lane ends with the same bits):
+// the event's (R, S1, S2) and, with GRAD, its 16 basis sums scaled by 2^R.
+// Used when events span many items, where one thread per event would walk
+// them serially.
 template <bool GRAD>
-__global__ __launch_bounds__(256) void event_merge_kernel(CombineArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= (int64_t)a.n_events * a.B) return;   // whole wavefronts
-  const int b = (int)(w / a.n_events), e = (int)(w % a.n_events);
+__device__ __forceinline__ Part3 wave_merge_event(const CombineArgs& a, int b, int e, int lane, double* G) {
   const double* P = a.part + (size_t)b * a.n_items * a.nf;
   Part3 m{0, 0, 0};
-  double G[GRAD ? 16 : 1];
 #pragma unroll
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
   double Rg = -1e300;
@@ -837,19 +834,14 @@ __global__ __launch_bounds__(256) void event_merge_kernel(CombineArgs a) {
       Rg = Rm;
     }
   }
-  if (lane == 0) {
-    double* o = a.ev_rec + ((size_t)b * a.n_events + e) * a.nf;
-    o[0] = m.R;
-    o[1] = m.S1;
-    o[2] = m.S2;
-    o[3] = 0.0;
-    if constexpr (GRAD) {
-      for (int p = 0; p < 16; ++p) o[4 + p] = G[p];
-    }
-  }
+  return m;
 }
 
-// PRE: each event's items were merged by event_merge_kernel into one record.
+template <bool GRAD>
+__device__ void merge_slices(const CombineArgs& a, int b, int n_slices, int lane);
+
+// PRE: each event's items are merged by one wavefront (wave_merge_event);
+// otherwise one thread walks an event's items.
 template <bool GRAD, bool KDE = false, bool PRE = false>
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   static_assert(!(GRAD && KDE), "the KDE numerator has no adjoint");
@@ -871,36 +863,9 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   for (int p = 0; p < (GRAD ? 16 : 1); ++p) accg[p] = 0;
   unsigned int flags = 0;
   const int slice = blockIdx.y, n_slices = gridDim.y;
-  for (int e = slice * blockDim.x + tid; e < a.n_events; e += n_slices * blockDim.x) {
-    Part3 m{0, 0, 0};
-    double G[GRAD ? 16 : 1];
-#pragma unroll
-    for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
-    double Rg = -1e300;
-    Part3 num{0, 0, 0};   // KDE: merged (R, sum of T) of the passing pixels
-    if constexpr (KDE) {
-      const double* r = a.kde + ((size_t)b * a.n_events + e) * NF_KDE;
-      num = Part3{r[0], r[1], 0.0};
-      m = Part3{r[0], r[2], r[3]};
-    }
-    const double* EP = PRE ? a.ev_rec + ((size_t)b * a.n_events + e) * a.nf : nullptr;
-    auto ate = [&](int sl, int f) { return PRE ? EP[f] : at(sl, f); };
-    const int sl0 = (KDE || PRE) ? 0 : a.ev_item_off[e];
-    const int sl1 = KDE ? 0 : (PRE ? 1 : a.ev_item_off[e + 1]);
-#pragma unroll 4
-    for (int sl = sl0; sl < sl1; ++sl) {
-      Part3 x{ate(sl, 0), ate(sl, 1), ate(sl, 2)};
-      if constexpr (GRAD) {
-        if (x.S1 > 0) {
-          if (x.R > Rg) {
-            for (int p = 0; p < 16; ++p) G[p] = (Rg > -1e299) ? ldexp(G[p], (int)(Rg - x.R)) : 0.0;
-            Rg = x.R;
-          }
-          for (int p = 0; p < 16; ++p) G[p] += ldexp(ate(sl, 4 + p), (int)(x.R - Rg));
-        }
-      }
-      m = pmerge(m, x);
-    }
+  // an event's ln L_i, N_eff,i and gradient terms from its merged sums m (and
+  // the KDE numerator's num); G shares the scale 2^m.R
+  auto finish_event = [&](int e, const Part3& m, Part3 num, const double* G) {
     double lnLe, neff;
     if constexpr (!KDE) num = m;
     if (valid && num.S1 > 0) {
@@ -920,10 +885,49 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     acc += lnLe;
     if constexpr (GRAD) {
       if (m.S1 > 0) {
-        // G and S1 share the scale 2^m.R (Rg == m.R)
         for (int p = 0; p < 16; ++p) accg[p] += G[p] / m.S1;
         n_ev_used += 1.0;
       }
+    }
+  };
+  if constexpr (PRE) {
+    // wavefront w of slice s takes events s * nw + w, then every n_slices * nw-th
+    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    for (int e = slice * nw + wave; e < a.n_events; e += n_slices * nw) {
+      double G[GRAD ? 16 : 1];
+      const Part3 m = wave_merge_event<GRAD>(a, b, e, lane, G);
+      if (lane == 0) finish_event(e, m, m, G);
+    }
+  } else {
+    for (int e = slice * blockDim.x + tid; e < a.n_events; e += n_slices * blockDim.x) {
+      Part3 m{0, 0, 0};
+      double G[GRAD ? 16 : 1];
+#pragma unroll
+      for (int p = 0; p < (GRAD ? 16 : 1); ++p) G[p] = 0;
+      double Rg = -1e300;
+      Part3 num{0, 0, 0};   // KDE: merged (R, sum of T) of the passing pixels
+      if constexpr (KDE) {
+        const double* r = a.kde + ((size_t)b * a.n_events + e) * NF_KDE;
+        num = Part3{r[0], r[1], 0.0};
+        m = Part3{r[0], r[2], r[3]};
+      }
+      const int sl0 = KDE ? 0 : a.ev_item_off[e];
+      const int sl1 = KDE ? 0 : a.ev_item_off[e + 1];
+#pragma unroll 4
+      for (int sl = sl0; sl < sl1; ++sl) {
+        Part3 x{at(sl, 0), at(sl, 1), at(sl, 2)};
+        if constexpr (GRAD) {
+          if (x.S1 > 0) {
+            if (x.R > Rg) {
+              for (int p = 0; p < 16; ++p) G[p] = (Rg > -1e299) ? ldexp(G[p], (int)(Rg - x.R)) : 0.0;
+              Rg = x.R;
+            }
+            for (int p = 0; p < 16; ++p) G[p] += ldexp(at(sl, 4 + p), (int)(x.R - Rg));
+          }
+        }
+        m = pmerge(m, x);
+      }
+      finish_event(e, m, num, G);
     }
   }
   // selection term: strided partial merges, then a fixed tree
@@ -1019,16 +1023,30 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
       }
     }
   }
+  if (n_slices > 1 && a.slice_ctr) {
+    // the point's last slice to finish merges the slice records, in slice
+    // order (so the result does not depend on which slice that is); the
+    // fences order each slice's record before its count, and the count before
+    // the last slice's reads
+    __shared__ int last;
+    if (tid == 0) {
+      __threadfence();
+      last = atomicAdd(a.slice_ctr + b, 1) == n_slices - 1;
+    }
+    __syncthreads();
+    if (last && tid < 64) {
+      __threadfence();
+      merge_slices<GRAD>(a, b, n_slices, tid);
+    }
+  }
 }
 
-// Merge of the slices of one point: one wavefront per point, lane k takes
-// slices k, k + 64, ..., then a fixed xor butterfly.  Its sums are commutative
-// and its selection merges exact power-of-two rescalings, so every lane ends
-// with the same bits and the result does not depend on timing.
+// Merge of the slices of one point by one wavefront: lane k takes slices k,
+// k + 64, ..., then a fixed xor butterfly.  Its sums are commutative and its
+// selection merges exact power-of-two rescalings, so every lane ends with the
+// same bits and the result does not depend on timing.
 template <bool GRAD>
-__global__ __launch_bounds__(64) void combine_slices_kernel(CombineArgs a, int n_slices) {
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x;
+__device__ void merge_slices(const CombineArgs& a, int b, int n_slices, int lane) {
   double acc = 0, nused = 0;
   int fl = 0;
   Part3 sel{0, 0, 0};
@@ -1190,28 +1208,17 @@ hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
+  if (a.n_slices > 1 && !a.slice_ctr) return hipErrorInvalidValue;   // the last slice merges the others
   const dim3 grid(a.B, a.n_slices);
   if (a.kde) {
     combine_kernel<false, true><<<grid, 256, 0, st>>>(a);
-  } else if (a.ev_rec) {
-    const int64_t threads = (int64_t)a.n_events * a.B * 64;
-    const unsigned blocks = (unsigned)((threads + 255) / 256);
-    if (grad) event_merge_kernel<true><<<blocks, 256, 0, st>>>(a);
-    else event_merge_kernel<false><<<blocks, 256, 0, st>>>(a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  } else if (a.wave_events) {
     if (grad) combine_kernel<true, false, true><<<grid, 256, 0, st>>>(a);
     else combine_kernel<false, false, true><<<grid, 256, 0, st>>>(a);
   } else if (grad) {
     combine_kernel<true><<<grid, 256, 0, st>>>(a);
   } else {
     combine_kernel<false><<<grid, 256, 0, st>>>(a);
-  }
-  if (a.n_slices > 1) {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (grad && !a.kde) combine_slices_kernel<true><<<a.B, 64, 0, st>>>(a, a.n_slices);
-    else combine_slices_kernel<false><<<a.B, 64, 0, st>>>(a, a.n_slices);
   }
   return hipGetLastError();
 }

@@ -275,9 +275,11 @@ def test_autotune_and_cache(mods, tmp_path):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_event_merge_paths(mods, precision):
-    """Events spanning many work items are merged by one wavefront each before
-    the combine (16-sample items: about 125 items per event); a few large items
-    per event take the serial merge.  Both against the oracle, with gradient."""
+    """Events spanning many work items are merged by one wavefront of the
+    combine each (16-sample items: about 125 items per event, and several
+    combine slices per point, merged by the last slice to finish); a few large
+    items per event take the serial merge.  Both against the oracle, with
+    gradient."""
     torch, O, synth = mods["torch"], mods["O"], mods["synth"]
     cat = synth.make_catalog("c1", n_events=4, n_inj=5000)
     lam = synth.draw_lambdas(5, seed=61)
