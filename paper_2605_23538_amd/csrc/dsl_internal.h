@@ -219,7 +219,7 @@ struct CombineArgs {
   int32_t n_slices;             // workgroups per point (events and injection slots strided over them)
   double* cpart;                // [B][n_slices][NF_CSLICE] slice records when n_slices > 1
   int32_t* slice_ctr;           // [B] finished slices per point (zeroed by setup): the last one merges
-                                // the slice records; null: a separate merge launch does
+                                // the slice records (small grids); null: a launch of its own does
 };
 
 }  // namespace dsl

@@ -1091,6 +1091,13 @@ __device__ void merge_slices(const CombineArgs& a, int b, int n_slices, int lane
   if (lane == 0) combine_finish<GRAD>(a, b, acc, nused, (unsigned int)fl, G, 1, sel, Gs, 1);
 }
 
+// The same merge as a launch of its own (one wavefront per point), for grids
+// without slice counters.
+template <bool GRAD>
+__global__ __launch_bounds__(64) void combine_slices_kernel(CombineArgs a, int n_slices) {
+  merge_slices<GRAD>(a, blockIdx.x, n_slices, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // sample packing (once per catalogue)
 // ---------------------------------------------------------------------------
@@ -1208,7 +1215,6 @@ hipError_t launch_gate_split(const GateSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
-  if (a.n_slices > 1 && !a.slice_ctr) return hipErrorInvalidValue;   // the last slice merges the others
   const dim3 grid(a.B, a.n_slices);
   if (a.kde) {
     combine_kernel<false, true><<<grid, 256, 0, st>>>(a);
@@ -1219,6 +1225,12 @@ hipError_t launch_combine(bool grad, const CombineArgs& a, hipStream_t st) {
     combine_kernel<true><<<grid, 256, 0, st>>>(a);
   } else {
     combine_kernel<false><<<grid, 256, 0, st>>>(a);
+  }
+  if (a.n_slices > 1 && !a.slice_ctr) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (grad && !a.kde) combine_slices_kernel<true><<<a.B, 64, 0, st>>>(a, a.n_slices);
+    else combine_slices_kernel<false><<<a.B, 64, 0, st>>>(a, a.n_slices);
   }
   return hipGetLastError();
 }
