@@ -302,6 +302,42 @@ def test_event_merge_paths(mods, precision):
         lik.close()
 
 
+def test_combine_slice_merge_paths(mods):
+    """The slices of a point are merged by the combine slice that finishes last
+    in small grids (points x slices <= 64) and by a launch of their own in
+    larger ones.  With 16-sample items the c1 catalogue's combine has several
+    slices per point, the same number at 2 and at 40 points, so the two points
+    shared by a 2-point call (in-kernel merge) and a 40-point call (separate
+    merge) must agree bitwise -- value, gradient and per-event terms -- and
+    match the oracle."""
+    torch, O, synth = mods["torch"], mods["O"], mods["synth"]
+    cat = synth.make_catalog("c1")
+    lam = synth.draw_lambdas(40, seed=83)
+    lam[0] = synth.fiducial_lambda()
+    out = {}
+    for B in (2, 40):
+        lik = mods["binding"].DarkSirenLikelihood(cat, precision="fp32")
+        lik.set_option("lambda_tile", 4)
+        lik.set_option("chunk", 16)
+        r = lik.loglike_grad(torch.tensor(lam[:B], device="cuda"), per_event=True)
+        torch.cuda.synchronize()
+        n_items = int(lik.info("n_items"))
+        assert n_items > 2 * 256 and (n_items + 255) // 256 <= 32   # 2..32 slices at both B
+        out[B] = {k: r[k][:2].cpu().numpy() for k in ("logL", "grad", "logL_event", "neff_event", "flags")}
+        lik.close()
+    log(f"  {n_items} items")
+    for k in out[2]:
+        a, b = out[2][k], out[40][k]
+        assert np.array_equal(a, b, equal_nan=True) if a.dtype.kind == "f" else np.array_equal(a, b), k
+    for b in range(2):
+        ref = O.loglike(cat, lam[b], grad=True, margins=True)
+        assert int(out[2]["flags"][b]) == ref["flags"]
+        check_events(out[2]["logL_event"][b], out[2]["neff_event"][b], ref, TOL_LOGL_FP32)
+        if not ref["flags"]:
+            assert rel_close(float(out[2]["logL"][b]), ref["logL"], TOL_LOGL_FP32)
+            check_grad(out[2]["grad"][b], ref["grad"])
+
+
 def test_degenerate_catalogues(mods):
     """An event with no pixels and an event whose pixels hold no samples (L_i = 0:
     flag 2, ln L = -inf), and injections all beyond z_max (alpha = 0: flag 4),
