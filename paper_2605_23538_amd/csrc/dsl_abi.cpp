@@ -1081,8 +1081,8 @@ int dsl_create(const dsl_catalog_desc* d_in, dsl_handle** out) {
   if ((rc = scratch_address(h->device, &h->scratch))) return rc;
   // a work list from the start (the one-point configuration's), so that the
   // allocation-free entry point always has one to read
-  const SweepCfg c1 = config_for(h.get(), 1, false);
-  if ((rc = build_items(h.get(), c1.chunk, c1.GL == 1 ? 64 : 1))) return rc;
+  const SweepCfg one = config_for(h.get(), 1, false);
+  if ((rc = build_items(h.get(), one.chunk, one.GL == 1 ? 64 : 1))) return rc;
   *out = h.release();
   return DSL_OK;
 }

@@ -305,8 +305,9 @@ def test_event_merge_paths(mods, precision):
 def test_combine_slice_merge_paths(mods):
     """The slices of a point are merged by the combine slice that finishes last
     in small grids (points x slices <= 64) and by a launch of their own in
-    larger ones.  With 16-sample items the c1 catalogue's combine has several
-    slices per point, the same number at 2 and at 40 points, so the two points
+    larger ones.  With 16-sample items the 10-event catalogue (20 000 samples,
+    10 000 injections) gives the combine several slices per point, the same
+    number at 2 and at 40 points, so the two points
     shared by a 2-point call (in-kernel merge) and a 40-point call (separate
     merge) must agree bitwise -- value, gradient and per-event terms -- and
     match the oracle."""
