@@ -837,6 +837,33 @@ __device__ __forceinline__ Part3 wave_merge_event(const CombineArgs& a, int b, i
   return m;
 }
 
+// Xor butterfly over a wavefront of the combine's partial results: the sums
+// of ln L_i, of events used and of their gradient terms G, the flags, and the
+// selection's exponent-tracked (R, S1, S2) with its basis sums Gs scaled by
+// 2^R.  The sums are commutative and the rescalings exact powers of two, so
+// every lane ends with the same bits.
+template <bool GRAD>
+__device__ __forceinline__ void wave_reduce(double& acc, double& nused, int& fl, double* G, Part3& sel, double* Gs) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    acc += __shfl_xor(acc, off);
+    nused += __shfl_xor(nused, off);
+    fl |= __shfl_xor(fl, off);
+    const Part3 o{__shfl_xor(sel.R, off), __shfl_xor(sel.S1, off), __shfl_xor(sel.S2, off)};
+    if constexpr (GRAD) {
+      const bool hs = sel.S1 > 0, ho = o.S1 > 0;
+      const double Rm = hs && ho ? fmax(sel.R, o.R) : (hs ? sel.R : o.R);
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        G[p] += __shfl_xor(G[p], off);
+        const double go = __shfl_xor(Gs[p], off);
+        Gs[p] = (hs ? ldexp(Gs[p], (int)(sel.R - Rm)) : 0.0) + (ho ? ldexp(go, (int)(o.R - Rm)) : 0.0);
+      }
+    }
+    sel = pmerge(sel, o);
+  }
+}
+
 template <bool GRAD>
 __device__ void merge_slices(const CombineArgs& a, int b, int n_slices, int lane);
 
@@ -852,10 +879,6 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
   const double* P = a.part;
   auto at = [&](int slot, int f) { return P[((size_t)b * a.n_items + slot) * a.nf + f]; };
   const bool valid = a.valid[b] != 0;
-  __shared__ double red[256];
-  __shared__ double redg[GRAD ? 16 : 1][256];
-  __shared__ unsigned int fl[256];
-  __shared__ Part3 rp[256];
   double acc = 0;
   double n_ev_used = 0;
   double accg[GRAD ? 16 : 1];
@@ -950,75 +973,60 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     }
     sel = pmerge(sel, x);
   }
-  red[tid] = acc;
-  fl[tid] = flags;
-  __shared__ double nused[256];
-  nused[tid] = n_ev_used;
-  rp[tid] = sel;
-  if constexpr (GRAD) {
-    for (int p = 0; p < 16; ++p) redg[p][tid] = accg[p];
-  }
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st) {
-      red[tid] += red[tid + st];
-      nused[tid] += nused[tid + st];
-      fl[tid] |= fl[tid + st];
-      if constexpr (GRAD) {
-        for (int p = 0; p < 16; ++p) redg[p][tid] += redg[p][tid + st];
+  // the block's partial results (256 threads): wavefronts 1-3 leave theirs in
+  // LDS, the lanes of wavefront 0 add the three counterparts in order, then an
+  // xor butterfly within wavefront 0
+  __shared__ double s_acc[256], s_n[256], s_g[GRAD ? 16 : 1][256], s_gs[GRAD ? 16 : 1][256];
+  __shared__ int s_fl[256];
+  __shared__ Part3 s_sel[256];
+  if (tid >= 64) {
+    s_acc[tid] = acc;
+    s_n[tid] = n_ev_used;
+    s_fl[tid] = (int)flags;
+    s_sel[tid] = sel;
+    if constexpr (GRAD) {
+      for (int p = 0; p < 16; ++p) {
+        s_g[p][tid] = accg[p];
+        s_gs[p][tid] = Gs[p];
       }
     }
-    __syncthreads();
-  }
-  // selection gradient needs a scale-aware tree: do it with the Part3 tree and
-  // per-thread G rescaled to the thread's own R (Rgs == rp[tid].R)
-  __shared__ double gsel[GRAD ? 16 : 1][256];
-  if constexpr (GRAD) {
-    for (int p = 0; p < 16; ++p) gsel[p][tid] = Gs[p];
   }
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    Part3 x, y;
-    double gx[GRAD ? 16 : 1];
-    if (tid < st) {
-      x = rp[tid];
-      y = rp[tid + st];
+  if (tid < 64) {
+    int fli = (int)flags;
+    for (int t = tid + 64; t < 256; t += 64) {
+      acc += s_acc[t];
+      n_ev_used += s_n[t];
+      fli |= s_fl[t];
+      const Part3 o = s_sel[t];
       if constexpr (GRAD) {
-        const bool hx = x.S1 > 0, hy = y.S1 > 0;
-        const double Rm = hx && hy ? fmax(x.R, y.R) : (hx ? x.R : y.R);
+        const bool hs = sel.S1 > 0, ho = o.S1 > 0;
+        const double Rm = hs && ho ? fmax(sel.R, o.R) : (hs ? sel.R : o.R);
         for (int p = 0; p < 16; ++p) {
-          const double a0 = hx ? ldexp(gsel[p][tid], (int)(x.R - Rm)) : 0.0;
-          const double a1 = hy ? ldexp(gsel[p][tid + st], (int)(y.R - Rm)) : 0.0;
-          gx[p] = a0 + a1;
+          accg[p] += s_g[p][t];
+          Gs[p] = (hs ? ldexp(Gs[p], (int)(sel.R - Rm)) : 0.0) + (ho ? ldexp(s_gs[p][t], (int)(o.R - Rm)) : 0.0);
         }
       }
+      sel = pmerge(sel, o);
     }
-    __syncthreads();
-    if (tid < st) {
-      rp[tid] = pmerge(x, y);
-      if constexpr (GRAD) {
-        for (int p = 0; p < 16; ++p) gsel[p][tid] = gx[p];
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n_slices == 1) {
-      combine_finish<GRAD>(a, b, red[0], nused[0], fl[0], GRAD ? &redg[0][0] : nullptr, 256, rp[0],
-                           GRAD ? &gsel[0][0] : nullptr, 256);
-    } else {
-      // slice record: acc, n_used, flags, selection (R, S1, S2), then 16 + 16 basis sums
-      double* o = a.cpart + ((size_t)b * n_slices + slice) * NF_CSLICE;
-      o[0] = red[0];
-      o[1] = nused[0];
-      o[2] = (double)fl[0];
-      o[3] = rp[0].R;
-      o[4] = rp[0].S1;
-      o[5] = rp[0].S2;
-      if constexpr (GRAD) {
-        for (int p = 0; p < 16; ++p) {
-          o[6 + p] = redg[p][0];
-          o[22 + p] = gsel[p][0];
+    wave_reduce<GRAD>(acc, n_ev_used, fli, accg, sel, Gs);
+    if (tid == 0) {
+      if (n_slices == 1) {
+        combine_finish<GRAD>(a, b, acc, n_ev_used, (unsigned int)fli, accg, 1, sel, Gs, 1);
+      } else {
+        // slice record: acc, n_used, flags, selection (R, S1, S2), then 16 + 16 basis sums
+        double* o = a.cpart + ((size_t)b * n_slices + slice) * NF_CSLICE;
+        o[0] = acc;
+        o[1] = n_ev_used;
+        o[2] = (double)fli;
+        o[3] = sel.R;
+        o[4] = sel.S1;
+        o[5] = sel.S2;
+        if constexpr (GRAD) {
+          for (int p = 0; p < 16; ++p) {
+            o[6 + p] = accg[p];
+            o[22 + p] = Gs[p];
+          }
         }
       }
     }
@@ -1070,24 +1078,7 @@ __device__ void merge_slices(const CombineArgs& a, int b, int n_slices, int lane
     }
     sel = pmerge(sel, x);
   }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    acc += __shfl_xor(acc, off);
-    nused += __shfl_xor(nused, off);
-    fl |= __shfl_xor(fl, off);
-    const Part3 o{__shfl_xor(sel.R, off), __shfl_xor(sel.S1, off), __shfl_xor(sel.S2, off)};
-    if constexpr (GRAD) {
-      const bool hs = sel.S1 > 0, ho = o.S1 > 0;
-      const double Rm = hs && ho ? fmax(sel.R, o.R) : (hs ? sel.R : o.R);
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        G[p] += __shfl_xor(G[p], off);
-        const double go = __shfl_xor(Gs[p], off);
-        Gs[p] = (hs ? ldexp(Gs[p], (int)(sel.R - Rm)) : 0.0) + (ho ? ldexp(go, (int)(o.R - Rm)) : 0.0);
-      }
-    }
-    sel = pmerge(sel, o);
-  }
+  wave_reduce<GRAD>(acc, nused, fl, G, sel, Gs);
   if (lane == 0) combine_finish<GRAD>(a, b, acc, nused, (unsigned int)fl, G, 1, sel, Gs, 1);
 }
 
