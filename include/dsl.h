@@ -228,8 +228,8 @@ int dsl_loglike_grad(dsl_handle* h, const double* d_lambda, int B, double* d_log
  * points needs about 0.75 GB: use dsl_loglike_grad there).  Every call on one
  * GPU shares that array, from every handle: calls that overlap in time on one
  * GPU (other streams, other threads) race and must be serialised by the
- * caller; the array keeps the last call's contents (nothing in it needs to
- * start at zero).
+ * caller; the array keeps the last call's contents (the only part that must
+ * start at zero, the work and slice counters, is zeroed by the call itself).
  */
 int dsl_loglike_grad_noalloc(dsl_handle* h, const double* d_lambda, int B, double* d_logL,
                              double* d_grad, double* d_logL_event, double* d_neff_event,
