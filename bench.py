@@ -275,8 +275,12 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "hbm_bytes": hbm_bytes, "hbm_bytes_kind": "measured" if traffic else "algorithmic",
                 "hbm_GBs": round(hbm_bytes / kt / 1e9, 1), "hbm_frac": round(hbm_bytes / kt / 1e9 / PEAK_HBM_GBS, 4),
-                "kernel": ("kde_tile_kernel<%s,%d> + kde_event_kernel"
-                           % ("float" if precision == "fp32" else "double", 64 if precision == "fp32" else 4)) if kde
+                "kernel": (("kde_tile_kernel<%s,%d> + kde_event_kernel"
+                            % ("float" if precision == "fp32" else "double",
+                               (64 if B >= 48 else 16 if B >= 12 else 4) if precision == "fp32" else 4))
+                           if B >= 4 else   # fewer points: the row kernel
+                           "kde_kernel<%s> + kde_event_kernel" % ("float" if precision == "fp32" else "double"))
+                if kde
                 else "sweep_kernel<%s,%d,%s>" % ("float" if precision == "fp32" else "double",
                                                  int(lik.info("lambda_tile_used")), "true" if grad else "false"),
                 "kernel_ms": round(kde_avg if kde else sweep_avg, 4),
